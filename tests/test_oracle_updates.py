@@ -1,0 +1,208 @@
+"""Pins of the oracle's single-spin updates and checkerboard sweeps
+(appendix A.1), and of the Schwinger-Dyson identity (appendix A.4).
+
+Overrelaxation: closed-form properties (unit length, s.h kept, involution,
+no move at h = 0) and exact energy conservation of a half-sweep.
+Heat-bath: the draw of cos(theta) = s.h/|h| against the closed-form CDF of
+the density exp(X c) on [-1, 1] (KS test), its mean against the Langevin
+function, a flat azimuth, the flat sphere at X = 0, and the two-spin system
+whose energy law is known exactly.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+
+def _cdf_cos(c, X):
+    """CDF of c in [-1, 1] with density ~ exp(X c)."""
+    c = np.asarray(c, dtype=np.float64)
+    if X == 0:
+        return (c + 1.0) / 2.0
+    return (np.exp(X * (c - 1.0)) - np.exp(-2.0 * X)) / (-np.expm1(-2.0 * X))
+
+
+def _frame(n):
+    a = np.array([1.0, 0, 0]) if abs(n[0]) < 0.9 else np.array([0, 1.0, 0])
+    e1 = np.cross(n, a); e1 /= np.linalg.norm(e1)
+    return e1, np.cross(n, e1)
+
+
+# ---------------------------------------------------------------- overrelaxation
+
+def test_overrelax_closed_form_properties(orc):
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        h = rng.standard_normal(3) * rng.uniform(0.01, 10)
+        s = rng.standard_normal(3); s /= np.linalg.norm(s)
+        t = orc.overrelax_spin(h, s)
+        assert abs(np.linalg.norm(t) - 1.0) < 1e-15
+        assert abs(t @ h - s @ h) < 1e-13 * np.linalg.norm(h)
+        # reflection about h: the component along h kept, the rest negated
+        hn = h / np.linalg.norm(h)
+        np.testing.assert_allclose(t, 2 * (s @ hn) * hn - s, atol=1e-14)
+        np.testing.assert_allclose(orc.overrelax_spin(h, t), s, atol=1e-14)
+    s = np.array([0.0, 0.6, 0.8])
+    np.testing.assert_array_equal(orc.overrelax_spin(np.zeros(3), s), s)
+
+
+@pytest.mark.parametrize("L", [4, 6])
+def test_overrelax_sweeps_conserve_energy(orc, L):
+    rng = np.random.default_rng(12 + L)
+    N = L ** 3
+    M = rng.standard_normal((3, N, 3, 3))
+    s = rng.standard_normal((N, 3)); s /= np.linalg.norm(s, axis=1)[:, None]
+    E0 = orc.energy(L, M, s)
+    before = s.copy()
+    for c in (0, 1):
+        orc.half_sweep(L, M, s, c, 0, 1.0, 0, 0, 0, 0, 0)
+        assert abs(orc.energy(L, M, s) - E0) <= 1e-12 * abs(E0)
+    assert np.abs(s - before).max() > 0.1  # the spins did move
+    for _ in range(10):
+        orc.sweep(L, M, s, 0, 1.0, 0, 0, 0, 0, 0)
+    assert abs(orc.energy(L, M, s) - E0) <= 10e-12 * abs(E0)
+    assert np.abs(np.linalg.norm(s, axis=1) - 1).max() < 1e-14
+
+
+def test_half_sweep_touches_only_its_colour(orc):
+    L = 4
+    rng = np.random.default_rng(13)
+    N = L ** 3
+    M = rng.standard_normal((3, N, 3, 3))
+    s = rng.standard_normal((N, 3)); s /= np.linalg.norm(s, axis=1)[:, None]
+    idx = np.arange(N)
+    col = (idx % L + (idx // L) % L + idx // (L * L)) % 2
+    for kind in (0, 1):
+        for c in (0, 1):
+            t = s.copy()
+            orc.half_sweep(L, M, t, c, kind, 0.7, 99, 3, 0, 1, 0)
+            np.testing.assert_array_equal(t[col != c], s[col != c])
+            assert (np.abs(t[col == c] - s[col == c]).max(axis=1) > 0).all()
+
+
+# --------------------------------------------------------------------- heat-bath
+
+@pytest.mark.parametrize("X", [0.0, 1e-3, 0.5, 3.0, 30.0])
+def test_heatbath_cos_theta_law(orc, X):
+    rng = np.random.default_rng(int(X * 1000) + 21)
+    n = rng.standard_normal(3); n /= np.linalg.norm(n)
+    beta = 0.8
+    h = n * (X / beta)
+    K = 20000
+    v = (rng.integers(0, 2 ** 23, K) + 0.5) / 2 ** 23
+    u2 = (rng.integers(0, 2 ** 23, K) + 0.5) / 2 ** 23
+    S = np.array([orc.heatbath_spin(h, beta, v[k], u2[k]) for k in range(K)])
+    assert np.abs(np.linalg.norm(S, axis=1) - 1).max() < 1e-14
+    axis = n if X > 0 else np.array([0.0, 0.0, 1.0])
+    c = S @ axis
+    p = stats.kstest(c, lambda x: _cdf_cos(x, X)).pvalue
+    assert p > 1e-3, p
+    if X > 0:
+        lang = 1.0 / np.tanh(X) - 1.0 / X
+        assert abs(c.mean() - lang) < 5 * c.std() / np.sqrt(K)
+    e1, e2 = _frame(axis)
+    phi = np.arctan2(S @ e2, S @ e1)
+    assert stats.kstest(phi, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-3
+    if X == 0:
+        assert abs((S[:, 2] ** 2).mean() - 1 / 3) < 5 * np.sqrt(4 / 45 / K)
+
+
+def test_heatbath_extreme_fields_are_finite(orc):
+    for X in (1e-300, 1e-18, 1e-7, 80.0, 1e4, 1e30):
+        for v in (2 ** -24, 0.5, 1 - 2 ** -24):
+            s = orc.heatbath_spin(np.array([0.0, 0.0, X]), 1.0, v, 0.3)
+            assert np.isfinite(s).all() and abs(np.linalg.norm(s) - 1) < 1e-14
+
+
+def test_heatbath_schwinger_dyson_single_site(orc):
+    """At fixed h: <2 T s.h - (h^2 - (s.h)^2)> = 0 (appendix A.4, per site)."""
+    rng = np.random.default_rng(22)
+    for T, hn in ((0.7, 1.3), (2.0, 0.4), (0.5, 5.0)):
+        h = rng.standard_normal(3); h *= hn / np.linalg.norm(h)
+        K = 40000
+        v = (rng.integers(0, 2 ** 23, K) + 0.5) / 2 ** 23
+        u2 = (rng.integers(0, 2 ** 23, K) + 0.5) / 2 ** 23
+        S = np.array([orc.heatbath_spin(h, 1.0 / T, v[k], u2[k]) for k in range(K)])
+        sh = S @ h
+        f = 2 * T * sh - (hn ** 2 - sh ** 2)
+        assert abs(f.mean()) < 5 * f.std() / np.sqrt(K)
+
+
+def _two_spin_lattice(Mbond):
+    L, N = 4, 64
+    M = np.zeros((3, N, 3, 3))
+    M[0, 0] = Mbond  # the one bond: site 0 -- site 1 (along x)
+    return L, N, M
+
+
+def _two_spin_energy_cdf(Mbond, beta, grid):
+    """Exact law of E = -s0^T M s1 under exp(-beta E) on two free unit spins:
+    for fixed s0, (M^T s0).s1 is uniform on [-r, r] with r = |M^T s0|."""
+    K = 200000
+    rng = np.random.default_rng(5)
+    s0 = rng.standard_normal((K, 3)); s0 /= np.linalg.norm(s0, axis=1)[:, None]
+    r = np.linalg.norm(s0 @ Mbond, axis=1)
+    # density of E: p(E) ~ exp(-beta E) * mean_s0[ 1{|E| <= r} / (2 r) ]
+    rs = np.sort(r)
+    inv = np.cumsum((1.0 / (2.0 * rs))[::-1])[::-1]  # sum over r >= |E|
+    pos = np.searchsorted(rs, np.abs(grid))
+    w = np.where(pos < K, inv[np.minimum(pos, K - 1)], 0.0) / K
+    dens = np.exp(-beta * (grid - grid[0])) * w
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (dens[1:] + dens[:-1]) * np.diff(grid))])
+    return cdf / cdf[-1]
+
+
+@pytest.mark.parametrize("kind", ["isotropic", "general"])
+def test_two_spin_energy_histogram(orc, kind):
+    rng = np.random.default_rng(31)
+    if kind == "isotropic":
+        Mbond = 1.3 * np.eye(3)
+    else:
+        Mbond = rng.standard_normal((3, 3))
+    L, N, M = _two_spin_lattice(Mbond)
+    beta = 1.5
+    s = orc.init_spins(L, 42, 0, 0, 0)
+    n_sweeps, thin = 12000, 3
+    Es = []
+    for t in range(n_sweeps):
+        orc.sweep(L, M, s, 1, beta, 42, t, 0, 0, 0)
+        if t % thin == 0:
+            Es.append(orc.energy(L, M, s))
+    Es = np.array(Es[50:])
+    if kind == "isotropic":
+        J = 1.3
+        cdf = lambda E: (np.exp(beta * J) - np.exp(-beta * np.clip(E, -J, J))) / (2 * np.sinh(beta * J))
+        # mean energy of the exact law: 1/beta - J coth(beta J)
+        mean_exact = 1.0 / beta - J / np.tanh(beta * J)
+        assert abs(Es.mean() - mean_exact) < 5 * Es.std() / np.sqrt(len(Es)) * 1.5
+    else:
+        rmax = np.linalg.norm(Mbond, 2)
+        grid = np.linspace(-rmax, rmax, 4001)
+        tab = _two_spin_energy_cdf(Mbond, beta, grid)
+        cdf = lambda E: np.interp(E, grid, tab)
+    assert stats.kstest(Es, cdf).pvalue > 1e-3
+    # the free spins stay uniform on the sphere
+    free = np.ones(N, bool); free[[0, 1]] = False
+    assert abs((s[free] ** 2).sum(axis=1).mean() - 1) < 1e-14
+
+
+@pytest.mark.slow
+def test_schwinger_dyson_lattice_equilibrium(orc):
+    """Lattice average of the identity of appendix A.4 at equilibrium."""
+    from oracle import OracleEnsemble
+    L = 4
+    N = L ** 3
+    rng = np.random.default_rng(41)
+    M = rng.standard_normal((3, N, 3, 3)).astype(np.float32)
+    T = 1.2
+    ens = OracleEnsemble(L, M, [T], 1, seed=77)
+    vals = []
+    for t in range(1500):
+        ens.step(1, 2)
+        if t >= 100:
+            sd1, sd2 = orc.sd_sums(L, ens.M, ens.spins[0, 0])
+            vals.append((2 * T * sd1 - sd2) / N)
+    vals = np.array(vals)
+    # blocked error bar (successive steps are correlated)
+    blocks = vals[: len(vals) // 20 * 20].reshape(20, -1).mean(axis=1)
+    err = blocks.std(ddof=1) / np.sqrt(len(blocks))
+    assert abs(vals.mean()) < 4 * err, (vals.mean(), err)
