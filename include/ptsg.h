@@ -1,0 +1,186 @@
+/*
+ * ptsg.h -- C ABI of the MI355X (gfx950) library for equilibrium Monte Carlo
+ * of the 3d Heisenberg spin glass with random anisotropic couplings
+ * (Baity-Jesi, Fernandez, Martin-Mayor, Sanz, arXiv:1309.1599).
+ *
+ * One Monte Carlo step of the paper (Sec. III and appendix A.1) is
+ *     pt_step(ctx, 1, L);   pt_swap(ctx);
+ * i.e. one heat-bath sweep, L overrelaxation sweeps, one parallel-tempering
+ * pass.  Measurements (Sec. II.B) are taken with pt_measure.
+ *
+ * Model (Sec. II.A, Eq. (1)).  N = L^3 unit 3-vectors on a periodic cubic
+ * lattice, site i = x + L*(y + L*z).  Each of the 3N bonds (i, i+e_mu),
+ * mu = 0,1,2 for x,y,z, carries a real 3x3 matrix M, and
+ *     H = - sum_i sum_mu  s_i^T M_{mu,i} s_{i+e_mu}.
+ * The paper's bond J*1 + D (D symmetric) is the special case M = J*1 + D;
+ * general matrices are accepted.  L must be even (checkerboard), 4 <= L <= 256.
+ *
+ * Ensemble.  A sample is one set of couplings; it is simulated at n_temps
+ * temperatures T_0 < T_1 < ... (the temperature slots) with n_replicas
+ * replicas each.  Chain (r, j) of a sample starts at slot j; parallel
+ * tempering permutes which chain sits at which slot and never moves spins
+ * (appendix A.1).
+ *
+ * Random numbers.  Philox4x32-10 (Salmon et al., SC'11) with key
+ * (seed lo32, seed hi32).  Counters (fourth word: tag<<28 | slot<<16 | rep<<8):
+ *   heat-bath at site i:      (i, hb_sweep, sample, 0<<28 | slot<<16 | rep<<8)
+ *   hot start at site i:      (i, 0, sample, 2<<28 | j<<16 | rep<<8)
+ *   PT pair (k, k+1):         (k, pt_pass, sample, 1<<28 | rep<<8)
+ * where hb_sweep counts the heat-bath sweeps done so far by the context and
+ * pt_pass the PT passes.  Uniforms: u = ((w >> 9) + 0.5) * 2^-23 from one
+ * word (heat-bath, hot start), u = ((w0>>6)*2^26 + (w1>>6) + 0.5) * 2^-52
+ * from two (PT).  So n_temps <= 4096 and n_replicas <= 256.
+ *
+ * Precision.  Spins and couplings are FP32 in device memory; energies,
+ * the PT acceptance and all measurement sums are FP64.
+ *
+ * Memory and streams.  Host arrays passed in are copied before the call
+ * returns.  Device memory is either one caller-owned workspace (see
+ * pt_workspace_size) or allocated by the library and released by pt_free.
+ * Work is queued on the context's stream (pt_set_stream); pt_step and
+ * pt_swap are asynchronous, every call that returns data to the host
+ * synchronises the stream.  A context is not thread-safe; distinct contexts
+ * are independent.
+ *
+ * Errors.  Every call returns a pt_status; no C++ exception crosses the ABI.
+ * pt_last_error() returns a message for the last failure on the calling
+ * thread.
+ */
+#ifndef PTSG_H
+#define PTSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pt_ctx pt_ctx;
+
+typedef enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,       /* invalid argument (message says which) */
+    PT_ENOMEM = -2,       /* workspace too small or allocation failed */
+    PT_EDEVICE = -3,      /* HIP runtime error (message holds its string) */
+    PT_ESTATE = -4,       /* call not valid in the context's state */
+    PT_EUNSUPPORTED = -5  /* valid but not supported by this build */
+} pt_status;
+
+/* Measurement selection bits for pt_measure. */
+enum {
+    PT_M_OVERLAP = 1u, /* overlap tensor Q^{ab}(k), Sec. II.B */
+    PT_M_CHIRAL = 2u,  /* chiral-glass overlap q_CG^mu(k), Sec. II.B */
+    PT_M_SD = 4u,      /* Schwinger-Dyson sums, appendix A.4 */
+    PT_M_ALL = 7u
+};
+
+/* One measurement record: replicas a < b of one sample at one temperature
+ * slot.  Fourier sums use (1/N) sum_x f(x) exp(+i k.x) with k = 0 or
+ * k = (2 pi / L) e_d, d = 0,1,2 (Sec. II.B):
+ *   q0[al*3+be]        = (1/N) sum_x s^a_al(x) s^b_be(x); q(0) = trace
+ *   qk_re/im[d][al*3+be] the same at k = (2 pi/L) e_d
+ *   cg0[mu]            = (1/N) sum_x zeta^a_{x,mu} zeta^b_{x,mu},
+ *                        zeta_{x,mu} = s_{x+e_mu} . (s_x cross s_{x-e_mu})
+ *   cgk_re/im[d][mu]   the same at k = (2 pi/L) e_d
+ *   sd1 = sum_x s.h, sd2 = sum_x (h^2 - (s.h)^2) for chains a and b;
+ *   E_a, E_b: energies (Eq. (1)) from the last pt_step / pt_set_spins.
+ * Fields not selected by `what` are zero. */
+typedef struct {
+    int32_t sample, tslot, rep_a, rep_b;
+    double beta, E_a, E_b;
+    double q0[9];
+    double qk_re[3][9], qk_im[3][9];
+    double cg0[3];
+    double cgk_re[3][3], cgk_im[3][3];
+    double sd1_a, sd2_a, sd1_b, sd2_b;
+} pt_meas;
+
+/* A batch of samples in one context.  Samples may differ in L and in their
+ * temperature grids; all share n_replicas and seed. */
+typedef struct {
+    int n_samples;
+    const int *L;                  /* [n_samples] linear sizes */
+    const int *n_temps;            /* [n_samples] */
+    const double *const *temps;    /* [n_samples] -> host [n_temps[s]], ascending, > 0 */
+    const float *const *couplings; /* [n_samples] -> host [3][L^3][3][3], finite */
+    int n_replicas;
+    uint64_t seed;
+    void *stream;                  /* hipStream_t for all work; NULL = null stream */
+    void *workspace;               /* caller device memory, or NULL: library allocates */
+    size_t workspace_bytes;        /* size of `workspace` (>= pt_workspace_size) */
+} pt_batch_desc;
+
+/* One sample (the single-lattice form of the API).  Equivalent to
+ * pt_init_batch with n_samples = 1, the null stream and library-owned
+ * memory.  Spins start hot (uniform on the sphere, Philox tag 2). */
+pt_status pt_init(pt_ctx **ctx, int L, const float *couplings, const double *temps,
+                  int n_temps, int n_replicas, uint64_t seed);
+
+/* Bytes of device workspace a batch needs (0 if the descriptor is invalid). */
+size_t pt_workspace_size(const pt_batch_desc *desc);
+
+/* Create a context for a batch of samples (see pt_batch_desc). */
+pt_status pt_init_batch(pt_ctx **ctx, const pt_batch_desc *desc);
+
+/* n_hb heat-bath sweeps then n_or overrelaxation sweeps of every chain
+ * (appendix A.1).  A sweep is the checkerboard half-sweep of colour 0
+ * ((x+y+z) even) then of colour 1.  Heat-bath draws s from
+ * P(s) ~ exp(s.h / T); overrelaxation maps s -> 2 h (h.s)/h^2 - s; both
+ * renormalise the spin.  The local field is
+ *   h_i = sum_mu [ M_{mu,i} s_{i+e_mu} + M_{mu,i-e_mu}^T s_{i-e_mu} ],
+ * i.e. -dH/ds_i.  Energies are refreshed at the end.  Asynchronous. */
+pt_status pt_step(pt_ctx *ctx, int n_hb, int n_or);
+
+/* One parallel-tempering pass per (sample, replica) (appendix A.1): for
+ * k = 0 .. n_temps-2 in order, exchange the chains at slots k and k+1 with
+ * probability min(1, exp((beta_k - beta_{k+1}) (E_k - E_{k+1}))).
+ * Asynchronous. */
+pt_status pt_swap(pt_ctx *ctx);
+
+/* Measure every (sample, slot, replica pair a < b) and copy the records,
+ * ordered by sample, slot, then pair, into out[cap].  *n_out receives the
+ * record count (sum over samples of n_temps * R(R-1)/2); PT_ENOMEM if cap is
+ * smaller.  PT_M_OVERLAP / PT_M_CHIRAL need n_replicas >= 2 (PT_ESTATE).
+ * Synchronous. */
+pt_status pt_measure(pt_ctx *ctx, unsigned what, pt_meas *out, size_t cap, size_t *n_out);
+
+/* Spins of the chain at (sample, replica, slot), host [N][3] FP32.
+ * pt_set_spins copies them in (no normalisation) and refreshes that
+ * sample's energies.  Synchronous. */
+pt_status pt_get_spins(pt_ctx *ctx, int sample, int rep, int tslot, float *out);
+pt_status pt_set_spins(pt_ctx *ctx, int sample, int rep, int tslot, const float *in);
+
+/* out[k] = index j of the chain now at slot k, for one (sample, replica). */
+pt_status pt_get_perm(pt_ctx *ctx, int sample, int rep, int32_t *out);
+
+/* Energies (Eq. (1)) of all chains, ordered by sample, replica, slot. */
+pt_status pt_get_energy(pt_ctx *ctx, double *out);
+
+/* Heat-bath sweeps and PT passes done so far (the Philox counters). */
+pt_status pt_get_counters(pt_ctx *ctx, uint64_t *hb_sweeps, uint64_t *pt_passes);
+
+/* Queue all further work on `stream` (hipStream_t, NULL = null stream). */
+pt_status pt_set_stream(pt_ctx *ctx, void *stream);
+
+/* Wait for all work queued by the context. */
+pt_status pt_sync(pt_ctx *ctx);
+
+/* Kernel timing.  When enabled, each sweep-kernel launch is bracketed by
+ * HIP events on the context's stream; pt_kernel_time synchronises and
+ * returns, for one kernel kind, the number of launches and their summed
+ * device time since profiling was (re-)enabled. */
+enum { PT_K_OVERRELAX = 0, PT_K_HEATBATH = 1 };
+pt_status pt_profile(pt_ctx *ctx, int enable);
+pt_status pt_kernel_time(pt_ctx *ctx, int kind, uint64_t *launches, double *ms);
+
+/* Release the context and any memory the library allocated. NULL is a no-op. */
+void pt_free(pt_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PTSG_H */

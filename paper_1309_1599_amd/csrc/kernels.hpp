@@ -1,0 +1,91 @@
+// kernels.hpp -- parameter blocks and launchers of the gfx950 kernels.
+//
+// Device layouts (all chosen for coalesced 64-lane access on CDNA):
+//
+//  spins   per chain: [colour 2][component 3][H] FP32, H = N/2.  A site
+//          (x,y,z) of colour c = (x+y+z)&1 sits at packed index
+//          p = (x>>1) + (L/2)*(y + L*z) of its colour plane, so a
+//          half-sweep reads its own colour and the other colour as dense
+//          component rows.  Chains of a sample are contiguous.
+//  cpl     per sample: [colour 2][54][H] FP32.  For the site at packed
+//          index p of colour c, element n*9 + a*3 + b is A_n[a][b], where
+//          A_0, A_2, A_4 are the bond matrices M_{mu,x} towards x+e_mu and
+//          A_1, A_3, A_5 are the transposes M_{mu,x-e_mu}^T of the bonds
+//          from x-e_mu, so that  h_x = sum_n A_n s_{nbr_n(x)}.  The
+//          duplication (each bond stored twice) buys fully coalesced,
+//          gather-free coupling loads.
+//  chains  global chain id = chain_base[sample] + rep*T + j, j = start slot.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptsg {
+
+constexpr int kSweepBlock = 256;   // threads per sweep workgroup (4 waves)
+constexpr int kMaxGroup = 128;     // chains per sweep workgroup (upper bound)
+constexpr int kMeasBlock = 256;
+constexpr int kOverlapQ = 45;      // plane partials: Q(0), Q(kx), Q(ky) re/im, 9 each
+constexpr int kChiralQ = 19;       // kappa(0), kappa(kx), kappa(ky) re/im, 3 each; 4 SD sums
+constexpr int kPlaneQ = kOverlapQ + kChiralQ;
+
+enum SweepKind { kOverrelax = 0, kHeatbath = 1, kEnergyOnly = 2 };
+
+struct SweepParams {
+    float *spins;
+    const float *cpl;
+    const int *samples;          // sample ids of this launch (one lattice class)
+    const int64_t *spin_base;    // per sample: float offset of its chain 0
+    const int64_t *cpl_base;     // per sample: float offset of its couplings
+    const int *chain_base;       // per sample: global id of its chain 0
+    const int *slot_of;          // per global chain: current temperature slot
+    const float *beta_of;        // per global chain: 1/T of its slot
+    double *e_part;              // [global chain][e_stride] energy partials
+    int e_stride;
+    int L, H, C, G, T;           // lattice, N/2, chains/sample, chains/workgroup, slots
+    int colour;
+    uint32_t hb_sweep, key0, key1;
+};
+
+struct SwapParams {
+    int *perm;                   // [sample][rep][T]: chain j at each slot
+    int *slot_of;
+    float *beta_of;
+    const double *E;             // per global chain
+    const double *betas;         // [sample][T] by slot
+    const int *chain_base, *perm_base, *beta_base, *n_temps;
+    int n_samples, R;
+    uint32_t pass, key0, key1;
+};
+
+struct EnergyParams {
+    const double *e_part;
+    int e_stride, n_blocks;      // partial blocks per chain for this class
+    const int *samples, *chain_base;
+    int C;
+    double *E;
+};
+
+struct MeasParams {
+    const float *spins;
+    const float *cpl;
+    const int *rec;              // [n_records][4]: sample, slot, rep_a, rep_b
+    const int *perm, *perm_base, *n_temps, *L, *chain_base, *twid_base;
+    const int64_t *spin_base, *cpl_base;
+    const double *twid;          // per lattice: cos(2 pi n/L), then sin, n < L
+    const double *E, *betas;
+    const int *beta_base;
+    double *part;                // [n_records][Lmax][kPlaneQ]
+    int Lmax, n_records;
+    unsigned what;
+    void *out;                   // device pt_meas[n_records]
+};
+
+hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_samples,
+                             hipStream_t st);
+hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st);
+hipError_t launch_swap(const SwapParams &p, hipStream_t st);
+hipError_t launch_init_spins(float *spins, int64_t spin_base, int L, int C, int T, int sample,
+                             uint32_t key0, uint32_t key1, hipStream_t st);
+hipError_t launch_measure(const MeasParams &p, hipStream_t st);
+
+}  // namespace ptsg

@@ -1,0 +1,280 @@
+// measure.hip -- overlap-tensor, chiral-overlap and Schwinger-Dyson sums
+// (Sec. II.B, appendix A.4) in FP64.
+//
+// Stage 1: one workgroup per (record, z plane) sums, over the plane's sites,
+// the products f(x) and f(x) exp(i k x_d) for k along x and y (the twiddle
+// of k along z is constant on a plane).  FP32 x FP32 products are exact in
+// FP64.  Lane sums are reduced by wave shuffles and then across the four
+// waves in a fixed order, so results are bit-reproducible.
+// Stage 2: one lane per record adds the planes in order, applies the
+// z twiddles and the 1/N normalisation, and writes the record.
+#include "../../include/ptsg.h"
+#include "kernels.hpp"
+
+namespace ptsg {
+
+namespace {
+
+// Plane-quantity slots.
+constexpr int kS0 = 0, kSxR = 9, kSxI = 18, kSyR = 27, kSyI = 36;       // overlap, 9 each
+constexpr int kK0 = 45, kKxR = 48, kKxI = 51, kKyR = 54, kKyI = 57;     // chiral, 3 each
+constexpr int kSD = 60;                                                  // sd1a sd2a sd1b sd2b
+
+struct Chain {
+    const float *s;
+    int L, Lh, H;
+    __device__ __forceinline__ int packed(int x, int y, int z) const
+    {
+        return (x >> 1) + Lh * (y + L * z);
+    }
+    __device__ __forceinline__ void get(int x, int y, int z, double v[3]) const
+    {
+        const int c = (x + y + z) & 1;
+        const int p = packed(x, y, z);
+        const float *o = s + c * 3 * H + p;
+        v[0] = o[0];
+        v[1] = o[H];
+        v[2] = o[2 * H];
+    }
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NQ>
+__device__ __forceinline__ void block_store(double (&acc)[NQ], double *dst)
+{
+    __shared__ double red[kMeasBlock / 64][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NQ; q += kMeasBlock) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kMeasBlock / 64; ++w) v += red[w][q];
+        dst[q] = v;
+    }
+}
+
+struct RecordChains {
+    Chain a, b;
+    int s, L;
+    const double *cw, *sw;
+};
+
+__device__ __forceinline__ RecordChains record_chains(const MeasParams &P, int rec)
+{
+    const int *rd = P.rec + 4 * rec;
+    const int s = rd[0], k = rd[1], ra = rd[2], rb = rd[3];
+    const int L = P.L[s], T = P.n_temps[s];
+    const int H = L * L * L / 2;
+    const int *perm = P.perm + P.perm_base[s];
+    const int ja = ra * T + perm[ra * T + k];
+    const int jb = rb * T + perm[rb * T + k];
+    RecordChains rc;
+    rc.a = Chain{P.spins + P.spin_base[s] + static_cast<int64_t>(ja) * 6 * H, L, L / 2, H};
+    rc.b = Chain{P.spins + P.spin_base[s] + static_cast<int64_t>(jb) * 6 * H, L, L / 2, H};
+    rc.s = s;
+    rc.L = L;
+    rc.cw = P.twid + P.twid_base[s];
+    rc.sw = rc.cw + L;
+    return rc;
+}
+
+__global__ __launch_bounds__(kMeasBlock) void overlap_plane_kernel(MeasParams P)
+{
+    const int rec = blockIdx.x, z = blockIdx.y;
+    const RecordChains rc = record_chains(P, rec);
+    const int L = rc.L;
+    if (z >= L) return;
+    double acc[45];
+#pragma unroll
+    for (int q = 0; q < 45; ++q) acc[q] = 0.0;
+    for (int idx = threadIdx.x; idx < L * L; idx += kMeasBlock) {
+        const int x = idx % L, y = idx / L;
+        double va[3], vb[3];
+        rc.a.get(x, y, z, va);
+        rc.b.get(x, y, z, vb);
+        const double cx = rc.cw[x], sx = rc.sw[x], cy = rc.cw[y], sy = rc.sw[y];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+#pragma unroll
+            for (int be = 0; be < 3; ++be) {
+                const int n = al * 3 + be;
+                const double q = va[al] * vb[be];
+                acc[kS0 + n] += q;
+                acc[kSxR + n] += q * cx;
+                acc[kSxI + n] += q * sx;
+                acc[kSyR + n] += q * cy;
+                acc[kSyI + n] += q * sy;
+            }
+        }
+    }
+    block_store<45>(acc, P.part + (static_cast<int64_t>(rec) * P.Lmax + z) * kPlaneQ);
+}
+
+__device__ __forceinline__ double chirality(const Chain &c, int x, int y, int z, int mu)
+{
+    const int L = c.L;
+    int p[3] = {x, y, z}, m[3] = {x, y, z};
+    p[mu] = (p[mu] + 1 == L) ? 0 : p[mu] + 1;
+    m[mu] = (m[mu] == 0) ? L - 1 : m[mu] - 1;
+    double u[3], v[3], w[3];
+    c.get(x, y, z, u);
+    c.get(p[0], p[1], p[2], v);
+    c.get(m[0], m[1], m[2], w);
+    // zeta = s_{x+e} . (s_x cross s_{x-e})
+    return v[0] * (u[1] * w[2] - u[2] * w[1]) + v[1] * (u[2] * w[0] - u[0] * w[2]) +
+           v[2] * (u[0] * w[1] - u[1] * w[0]);
+}
+
+// FP64 local field from the packed couplings (h = sum_n A_n s_nbr).
+__device__ __forceinline__ void field64(const Chain &c, const float *cpl, int x, int y, int z,
+                                        double h[3])
+{
+    const int L = c.L, H = c.H;
+    const int col = (x + y + z) & 1;
+    const float *A = cpl + static_cast<int64_t>(col) * 54 * H + c.packed(x, y, z);
+    const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+    const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+    const int zp = z + 1 == L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
+    const int nx[6] = {xp, xm, x, x, x, x};
+    const int ny[6] = {y, y, yp, ym, y, y};
+    const int nz[6] = {z, z, z, z, zp, zm};
+    h[0] = h[1] = h[2] = 0.0;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        double v[3];
+        c.get(nx[n], ny[n], nz[n], v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                h[a] += static_cast<double>(A[static_cast<int64_t>(n * 9 + a * 3 + b) * H]) * v[b];
+    }
+}
+
+__global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
+{
+    const int rec = blockIdx.x, z = blockIdx.y;
+    const RecordChains rc = record_chains(P, rec);
+    const int L = rc.L;
+    if (z >= L) return;
+    const bool chi = P.what & PT_M_CHIRAL, sd = P.what & PT_M_SD;
+    const float *cpl = P.cpl + P.cpl_base[rc.s];
+    double acc[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) acc[q] = 0.0;
+    for (int idx = threadIdx.x; idx < L * L; idx += kMeasBlock) {
+        const int x = idx % L, y = idx / L;
+        if (chi) {
+            const double cx = rc.cw[x], sx = rc.sw[x], cy = rc.cw[y], sy = rc.sw[y];
+#pragma unroll
+            for (int mu = 0; mu < 3; ++mu) {
+                const double kap = chirality(rc.a, x, y, z, mu) * chirality(rc.b, x, y, z, mu);
+                acc[mu] += kap;
+                acc[3 + mu] += kap * cx;
+                acc[6 + mu] += kap * sx;
+                acc[9 + mu] += kap * cy;
+                acc[12 + mu] += kap * sy;
+            }
+        }
+        if (sd) {
+            double h[3], v[3];
+            field64(rc.a, cpl, x, y, z, h);
+            rc.a.get(x, y, z, v);
+            double sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+            acc[15] += sh;
+            acc[16] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
+            field64(rc.b, cpl, x, y, z, h);
+            rc.b.get(x, y, z, v);
+            sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+            acc[17] += sh;
+            acc[18] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
+        }
+    }
+    block_store<19>(acc, P.part + (static_cast<int64_t>(rec) * P.Lmax + z) * kPlaneQ + kOverlapQ);
+}
+
+__global__ void finalize_kernel(MeasParams P)
+{
+    const int rec = blockIdx.x * blockDim.x + threadIdx.x;
+    if (rec >= P.n_records) return;
+    const int *rd = P.rec + 4 * rec;
+    const int s = rd[0], k = rd[1], ra = rd[2], rb = rd[3];
+    const int L = P.L[s], T = P.n_temps[s];
+    const double invN = 1.0 / (static_cast<double>(L) * L * L);
+    const double *cw = P.twid + P.twid_base[s], *sw = cw + L;
+    const double *part = P.part + static_cast<int64_t>(rec) * P.Lmax * kPlaneQ;
+    pt_meas &m = static_cast<pt_meas *>(P.out)[rec];
+    m.sample = s;
+    m.tslot = k;
+    m.rep_a = ra;
+    m.rep_b = rb;
+    m.beta = P.betas[P.beta_base[s] + k];
+    const int *perm = P.perm + P.perm_base[s];
+    m.E_a = P.E[P.chain_base[s] + ra * T + perm[ra * T + k]];
+    m.E_b = P.E[P.chain_base[s] + rb * T + perm[rb * T + k]];
+    double sums[kPlaneQ], zr[9], zi[9], kzr[3], kzi[3];
+    for (int q = 0; q < kPlaneQ; ++q) sums[q] = 0.0;
+    for (int n = 0; n < 9; ++n) zr[n] = zi[n] = 0.0;
+    for (int n = 0; n < 3; ++n) kzr[n] = kzi[n] = 0.0;
+    for (int z = 0; z < L; ++z) {
+        const double *pz = part + static_cast<int64_t>(z) * kPlaneQ;
+        for (int q = 0; q < kPlaneQ; ++q) sums[q] += pz[q];
+        for (int n = 0; n < 9; ++n) {
+            zr[n] += pz[kS0 + n] * cw[z];
+            zi[n] += pz[kS0 + n] * sw[z];
+        }
+        for (int n = 0; n < 3; ++n) {
+            kzr[n] += pz[kK0 + n] * cw[z];
+            kzi[n] += pz[kK0 + n] * sw[z];
+        }
+    }
+    const bool ovl = P.what & PT_M_OVERLAP, chi = P.what & PT_M_CHIRAL, sd = P.what & PT_M_SD;
+    for (int n = 0; n < 9; ++n) {
+        m.q0[n] = ovl ? sums[kS0 + n] * invN : 0.0;
+        m.qk_re[0][n] = ovl ? sums[kSxR + n] * invN : 0.0;
+        m.qk_im[0][n] = ovl ? sums[kSxI + n] * invN : 0.0;
+        m.qk_re[1][n] = ovl ? sums[kSyR + n] * invN : 0.0;
+        m.qk_im[1][n] = ovl ? sums[kSyI + n] * invN : 0.0;
+        m.qk_re[2][n] = ovl ? zr[n] * invN : 0.0;
+        m.qk_im[2][n] = ovl ? zi[n] * invN : 0.0;
+    }
+    for (int n = 0; n < 3; ++n) {
+        m.cg0[n] = chi ? sums[kK0 + n] * invN : 0.0;
+        m.cgk_re[0][n] = chi ? sums[kKxR + n] * invN : 0.0;
+        m.cgk_im[0][n] = chi ? sums[kKxI + n] * invN : 0.0;
+        m.cgk_re[1][n] = chi ? sums[kKyR + n] * invN : 0.0;
+        m.cgk_im[1][n] = chi ? sums[kKyI + n] * invN : 0.0;
+        m.cgk_re[2][n] = chi ? kzr[n] * invN : 0.0;
+        m.cgk_im[2][n] = chi ? kzi[n] * invN : 0.0;
+    }
+    m.sd1_a = sd ? sums[kSD + 0] : 0.0;
+    m.sd2_a = sd ? sums[kSD + 1] : 0.0;
+    m.sd1_b = sd ? sums[kSD + 2] : 0.0;
+    m.sd2_b = sd ? sums[kSD + 3] : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_measure(const MeasParams &p, hipStream_t st)
+{
+    if (p.n_records == 0) return hipSuccess;
+    const dim3 grid(p.n_records, p.Lmax);
+    if (p.what & PT_M_OVERLAP)
+        hipLaunchKernelGGL(overlap_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+    if (p.what & (PT_M_CHIRAL | PT_M_SD))
+        hipLaunchKernelGGL(chiral_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+    hipLaunchKernelGGL(finalize_kernel, dim3((p.n_records + 63) / 64), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace ptsg

@@ -1,0 +1,738 @@
+// ptsg.hip -- the C ABI (include/ptsg.h): validation, device memory plan,
+// host-side packing of couplings, and the launch sequence of a step.
+#include "../../include/ptsg.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace ptsg;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define PT_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(PT_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// One lattice class: samples sharing L and the number of temperatures, swept
+// by the same launches.
+struct LatticeClass {
+    int L = 0, T = 0, C = 0, G = 1, n_site_blocks = 0;
+    std::vector<int> samples;
+    int *d_samples = nullptr;
+};
+
+// Device memory plan of a batch: byte offsets into one workspace.
+struct Plan {
+    int S = 0, R = 0, n_chains = 0, Lmax = 0, n_records = 0, e_stride = 1, twid_len = 0;
+    std::vector<int> L, T, chain_base, perm_base, beta_base, twid_base;
+    std::vector<int64_t> spin_base, cpl_base;
+    int64_t spin_floats = 0, cpl_floats = 0;
+    int total_perm = 0;
+    size_t off_spins = 0, off_cpl = 0, off_slot = 0, off_beta_of = 0, off_E = 0, off_perm = 0,
+           off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0, off_mpart = 0,
+           off_meas = 0, off_classes = 0, bytes = 0;
+    size_t meta_ints = 0;
+};
+
+std::string validate(const pt_batch_desc *d)
+{
+    if (!d) return "descriptor is NULL";
+    if (d->n_samples < 1) return "n_samples must be >= 1";
+    if (!d->L || !d->n_temps || !d->temps || !d->couplings) return "NULL array in descriptor";
+    if (d->n_replicas < 1 || d->n_replicas > 256) return "n_replicas must be in [1, 256]";
+    for (int s = 0; s < d->n_samples; ++s) {
+        const int L = d->L[s];
+        if (L < 4 || L > 256 || (L & 1))
+            return "sample " + std::to_string(s) + ": L must be even and in [4, 256]";
+        const int T = d->n_temps[s];
+        if (T < 1 || T > 4096) return "sample " + std::to_string(s) + ": n_temps must be in [1, 4096]";
+        if (!d->temps[s] || !d->couplings[s]) return "sample " + std::to_string(s) + ": NULL pointer";
+        for (int k = 0; k < T; ++k) {
+            const double t = d->temps[s][k];
+            if (!(t > 0.0) || !std::isfinite(t))
+                return "sample " + std::to_string(s) + ": temperatures must be finite and > 0";
+            if (k > 0 && !(t > d->temps[s][k - 1]))
+                return "sample " + std::to_string(s) + ": temperatures must be strictly ascending";
+        }
+    }
+    return "";
+}
+
+Plan make_plan(const pt_batch_desc *d)
+{
+    Plan p;
+    p.S = d->n_samples;
+    p.R = d->n_replicas;
+    int chains = 0, perm = 0, betas = 0, twid = 0;
+    int64_t spins = 0, cpl = 0;
+    int max_blocks = 1;
+    for (int s = 0; s < p.S; ++s) {
+        const int L = d->L[s], T = d->n_temps[s];
+        const int64_t N = static_cast<int64_t>(L) * L * L;
+        p.L.push_back(L);
+        p.T.push_back(T);
+        p.chain_base.push_back(chains);
+        p.perm_base.push_back(perm);
+        p.beta_base.push_back(betas);
+        p.twid_base.push_back(twid);
+        p.spin_base.push_back(spins);
+        p.cpl_base.push_back(cpl);
+        chains += p.R * T;
+        perm += p.R * T;
+        betas += T;
+        twid += 2 * L;
+        spins += static_cast<int64_t>(p.R) * T * 3 * N;
+        cpl += 54 * N;
+        p.Lmax = std::max(p.Lmax, L);
+        max_blocks = std::max<int>(max_blocks, static_cast<int>((N / 2 + kSweepBlock - 1) / kSweepBlock));
+        p.n_records += T * p.R * (p.R - 1) / 2;
+    }
+    p.n_chains = chains;
+    p.total_perm = perm;
+    p.spin_floats = spins;
+    p.cpl_floats = cpl;
+    p.e_stride = max_blocks;
+    p.twid_len = twid;
+    p.meta_ints = 0;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    p.off_spins = take(sizeof(float) * static_cast<size_t>(spins));
+    p.off_cpl = take(sizeof(float) * static_cast<size_t>(cpl));
+    p.off_slot = take(sizeof(int) * chains);
+    p.off_beta_of = take(sizeof(float) * chains);
+    p.off_E = take(sizeof(double) * chains);
+    p.off_perm = take(sizeof(int) * perm);
+    p.off_betas = take(sizeof(double) * betas);
+    p.off_epart = take(sizeof(double) * static_cast<size_t>(chains) * p.e_stride);
+    p.off_twid = take(sizeof(double) * twid);
+    // per-sample int tables: L, n_temps, chain_base, perm_base, beta_base, twid_base
+    p.off_meta = take(sizeof(int) * 6 * p.S + 2 * sizeof(int64_t) * p.S + kAlign);
+    p.off_rec = take(sizeof(int) * 4 * std::max(1, p.n_records));
+    p.off_mpart = take(sizeof(double) * static_cast<size_t>(std::max(1, p.n_records)) * p.Lmax * kPlaneQ);
+    p.off_meas = take(sizeof(pt_meas) * std::max(1, p.n_records));
+    p.off_classes = take(sizeof(int) * p.S);
+    p.bytes = o;
+    return p;
+}
+
+struct Event {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct pt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t seed = 0, hb_sweeps = 0, pt_passes = 0;
+    Plan plan;
+    std::vector<LatticeClass> classes;
+    char *ws = nullptr;
+    bool own_ws = false;
+    // device views
+    float *spins = nullptr, *cpl = nullptr, *beta_of = nullptr;
+    int *slot_of = nullptr, *perm = nullptr, *rec = nullptr;
+    double *E = nullptr, *betas = nullptr, *epart = nullptr, *twid = nullptr, *mpart = nullptr;
+    pt_meas *meas = nullptr;
+    int *d_L = nullptr, *d_T = nullptr, *d_chain_base = nullptr, *d_perm_base = nullptr,
+        *d_beta_base = nullptr, *d_twid_base = nullptr;
+    int64_t *d_spin_base = nullptr, *d_cpl_base = nullptr;
+    // profiling
+    bool profiling = false;
+    std::vector<std::pair<int, Event>> pending;
+    std::vector<Event> free_events;
+    uint64_t prof_launches[2] = {0, 0};
+    double prof_ms[2] = {0.0, 0.0};
+};
+
+namespace {
+
+SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour)
+{
+    SweepParams p{};
+    p.spins = c->spins;
+    p.cpl = c->cpl;
+    p.samples = k.d_samples;
+    p.spin_base = c->d_spin_base;
+    p.cpl_base = c->d_cpl_base;
+    p.chain_base = c->d_chain_base;
+    p.slot_of = c->slot_of;
+    p.beta_of = c->beta_of;
+    p.e_part = c->epart;
+    p.e_stride = c->plan.e_stride;
+    p.L = k.L;
+    p.H = k.L * k.L * k.L / 2;
+    p.C = k.C;
+    p.G = k.G;
+    p.T = k.T;
+    p.colour = colour;
+    p.hb_sweep = static_cast<uint32_t>(c->hb_sweeps);
+    p.key0 = static_cast<uint32_t>(c->seed);
+    p.key1 = static_cast<uint32_t>(c->seed >> 32);
+    return p;
+}
+
+pt_status get_event(pt_ctx *c, Event &ev)
+{
+    if (!c->free_events.empty()) {
+        ev = c->free_events.back();
+        c->free_events.pop_back();
+        return PT_OK;
+    }
+    PT_HIP(hipEventCreate(&ev.a));
+    PT_HIP(hipEventCreate(&ev.b));
+    return PT_OK;
+}
+
+pt_status drain_events(pt_ctx *c)
+{
+    if (c->pending.empty()) return PT_OK;
+    PT_HIP(hipStreamSynchronize(c->stream));
+    for (auto &pe : c->pending) {
+        float ms = 0.0f;
+        PT_HIP(hipEventElapsedTime(&ms, pe.second.a, pe.second.b));
+        c->prof_ms[pe.first] += ms;
+        c->prof_launches[pe.first] += 1;
+        c->free_events.push_back(pe.second);
+    }
+    c->pending.clear();
+    return PT_OK;
+}
+
+// One half-sweep of every class; `energy` fuses the energy partials.
+pt_status half_sweep_all(pt_ctx *c, int kind, int colour, bool energy)
+{
+    for (const auto &k : c->classes) {
+        const SweepParams p = sweep_params(c, k, colour);
+        Event ev;
+        const bool timed = c->profiling && kind != kEnergyOnly;
+        if (timed) {
+            if (c->pending.size() >= 4096) {
+                pt_status st = drain_events(c);
+                if (st != PT_OK) return st;
+            }
+            pt_status st = get_event(c, ev);
+            if (st != PT_OK) return st;
+            PT_HIP(hipEventRecord(ev.a, c->stream));
+        }
+        PT_HIP(launch_half_sweep(kind, energy, p, static_cast<int>(k.samples.size()), c->stream));
+        if (timed) {
+            PT_HIP(hipEventRecord(ev.b, c->stream));
+            c->pending.push_back({kind == kOverrelax ? PT_K_OVERRELAX : PT_K_HEATBATH, ev});
+        }
+        if (energy) {
+            EnergyParams e{};
+            e.e_part = c->epart;
+            e.e_stride = c->plan.e_stride;
+            e.n_blocks = k.n_site_blocks;
+            e.samples = k.d_samples;
+            e.chain_base = c->d_chain_base;
+            e.C = k.C;
+            e.E = c->E;
+            PT_HIP(launch_energy_finalize(e, static_cast<int>(k.samples.size()), c->stream));
+        }
+    }
+    return PT_OK;
+}
+
+pt_status refresh_energies(pt_ctx *c) { return half_sweep_all(c, kEnergyOnly, 1, true); }
+
+// Chains per workgroup: enough workgroups to cover the chip several times,
+// as many chains as possible sharing one coupling load.
+int choose_group(int H, int C, int n_samples)
+{
+    const int blocks = (H + kSweepBlock - 1) / kSweepBlock * n_samples;
+    int G = std::min(C, kMaxGroup);
+    while (G > 1 && static_cast<int64_t>(blocks) * ((C + G - 1) / G) < 2048) G = (G + 1) / 2;
+    return G;
+}
+
+void pack_couplings(int L, const float *M, float *out)
+{
+    // out[colour][54][H]; see kernels.hpp.  M is [3][N][3][3].
+    const int N = L * L * L, H = N / 2, Lh = L / 2;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int i = x + L * (y + L * z);
+                const int col = (x + y + z) & 1;
+                const int p = (x >> 1) + Lh * (y + L * z);
+                const int back[3] = {((x + L - 1) % L) + L * (y + L * z),
+                                     x + L * (((y + L - 1) % L) + L * z),
+                                     x + L * (y + L * ((z + L - 1) % L))};
+                float *o = out + static_cast<int64_t>(col) * 54 * H + p;
+                for (int mu = 0; mu < 3; ++mu) {
+                    const float *fw = M + (static_cast<int64_t>(mu) * N + i) * 9;
+                    const float *bw = M + (static_cast<int64_t>(mu) * N + back[mu]) * 9;
+                    for (int a = 0; a < 3; ++a)
+                        for (int b = 0; b < 3; ++b) {
+                            o[static_cast<int64_t>((2 * mu) * 9 + a * 3 + b) * H] = fw[a * 3 + b];
+                            o[static_cast<int64_t>((2 * mu + 1) * 9 + a * 3 + b) * H] = bw[b * 3 + a];
+                        }
+                }
+            }
+}
+
+pt_status check_ctx(pt_ctx *c)
+{
+    if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
+    PT_HIP(hipSetDevice(c->device));
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pt_last_error(void) { return g_err.c_str(); }
+
+size_t pt_workspace_size(const pt_batch_desc *desc)
+{
+    if (!validate(desc).empty()) return 0;
+    return make_plan(desc).bytes;
+}
+
+pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
+{
+    if (!out) return fail(PT_EINVAL, "ctx output pointer is NULL");
+    *out = nullptr;
+    const std::string why = validate(d);
+    if (!why.empty()) return fail(PT_EINVAL, why);
+    for (int s = 0; s < d->n_samples; ++s) {
+        const int64_t n = 27ll * d->L[s] * d->L[s] * d->L[s];
+        for (int64_t q = 0; q < n; ++q)
+            if (!std::isfinite(d->couplings[s][q]))
+                return fail(PT_EINVAL, "sample " + std::to_string(s) + ": non-finite coupling");
+    }
+    pt_ctx *c = new (std::nothrow) pt_ctx();
+    if (!c) return fail(PT_ENOMEM, "host allocation failed");
+    struct Guard {
+        pt_ctx *&c;
+        ~Guard() { if (c) pt_free(c); }
+    } guard{c};
+
+    if (hipGetDevice(&c->device) != hipSuccess) return fail(PT_EDEVICE, "no HIP device");
+    c->stream = static_cast<hipStream_t>(d->stream);
+    c->seed = d->seed;
+    c->plan = make_plan(d);
+    Plan &P = c->plan;
+    if (d->workspace) {
+        if (d->workspace_bytes < P.bytes)
+            return fail(PT_ENOMEM, "workspace of " + std::to_string(d->workspace_bytes) +
+                                       " bytes is smaller than the " + std::to_string(P.bytes) +
+                                       " required");
+        if (reinterpret_cast<uintptr_t>(d->workspace) % kAlign)
+            return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+        c->ws = static_cast<char *>(d->workspace);
+    } else {
+        void *w = nullptr;
+        if (hipMalloc(&w, P.bytes) != hipSuccess)
+            return fail(PT_ENOMEM, "hipMalloc of " + std::to_string(P.bytes) + " bytes failed");
+        c->ws = static_cast<char *>(w);
+        c->own_ws = true;
+    }
+    char *w = c->ws;
+    c->spins = reinterpret_cast<float *>(w + P.off_spins);
+    c->cpl = reinterpret_cast<float *>(w + P.off_cpl);
+    c->slot_of = reinterpret_cast<int *>(w + P.off_slot);
+    c->beta_of = reinterpret_cast<float *>(w + P.off_beta_of);
+    c->E = reinterpret_cast<double *>(w + P.off_E);
+    c->perm = reinterpret_cast<int *>(w + P.off_perm);
+    c->betas = reinterpret_cast<double *>(w + P.off_betas);
+    c->epart = reinterpret_cast<double *>(w + P.off_epart);
+    c->twid = reinterpret_cast<double *>(w + P.off_twid);
+    c->rec = reinterpret_cast<int *>(w + P.off_rec);
+    c->mpart = reinterpret_cast<double *>(w + P.off_mpart);
+    c->meas = reinterpret_cast<pt_meas *>(w + P.off_meas);
+    {
+        char *m = w + P.off_meta;
+        c->d_spin_base = reinterpret_cast<int64_t *>(m);
+        c->d_cpl_base = c->d_spin_base + P.S;
+        int *ip = reinterpret_cast<int *>(c->d_cpl_base + P.S);
+        c->d_L = ip;
+        c->d_T = ip + P.S;
+        c->d_chain_base = ip + 2 * P.S;
+        c->d_perm_base = ip + 3 * P.S;
+        c->d_beta_base = ip + 4 * P.S;
+        c->d_twid_base = ip + 5 * P.S;
+    }
+    hipStream_t st = c->stream;
+    // per-sample tables
+    {
+        std::vector<char> meta(2 * sizeof(int64_t) * P.S + 6 * sizeof(int) * P.S);
+        int64_t *lp = reinterpret_cast<int64_t *>(meta.data());
+        std::copy(P.spin_base.begin(), P.spin_base.end(), lp);
+        std::copy(P.cpl_base.begin(), P.cpl_base.end(), lp + P.S);
+        int *ip = reinterpret_cast<int *>(lp + 2 * P.S);
+        std::copy(P.L.begin(), P.L.end(), ip);
+        std::copy(P.T.begin(), P.T.end(), ip + P.S);
+        std::copy(P.chain_base.begin(), P.chain_base.end(), ip + 2 * P.S);
+        std::copy(P.perm_base.begin(), P.perm_base.end(), ip + 3 * P.S);
+        std::copy(P.beta_base.begin(), P.beta_base.end(), ip + 4 * P.S);
+        std::copy(P.twid_base.begin(), P.twid_base.end(), ip + 5 * P.S);
+        PT_HIP(hipMemcpy(w + P.off_meta, meta.data(), meta.size(), hipMemcpyHostToDevice));
+    }
+    // temperatures, permutation, slots, twiddles, measurement records
+    {
+        std::vector<double> betas, twid;
+        std::vector<int> perm, slot;
+        std::vector<float> beta_of;
+        std::vector<int> rec;
+        for (int s = 0; s < P.S; ++s) {
+            const int T = P.T[s], L = P.L[s];
+            for (int k = 0; k < T; ++k) betas.push_back(1.0 / d->temps[s][k]);
+            for (int r = 0; r < P.R; ++r)
+                for (int j = 0; j < T; ++j) {
+                    perm.push_back(j);
+                    slot.push_back(j);
+                    beta_of.push_back(static_cast<float>(1.0 / d->temps[s][j]));
+                }
+            const double two_pi = 6.283185307179586476925286766559;
+            for (int n = 0; n < L; ++n) twid.push_back(std::cos(two_pi * n / L));
+            for (int n = 0; n < L; ++n) twid.push_back(std::sin(two_pi * n / L));
+            for (int k = 0; k < T; ++k)
+                for (int a = 0; a < P.R; ++a)
+                    for (int b = a + 1; b < P.R; ++b) {
+                        rec.push_back(s);
+                        rec.push_back(k);
+                        rec.push_back(a);
+                        rec.push_back(b);
+                    }
+        }
+        PT_HIP(hipMemcpy(c->betas, betas.data(), betas.size() * sizeof(double), hipMemcpyHostToDevice));
+        PT_HIP(hipMemcpy(c->perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+        PT_HIP(hipMemcpy(c->slot_of, slot.data(), slot.size() * sizeof(int), hipMemcpyHostToDevice));
+        PT_HIP(hipMemcpy(c->beta_of, beta_of.data(), beta_of.size() * sizeof(float), hipMemcpyHostToDevice));
+        PT_HIP(hipMemcpy(c->twid, twid.data(), twid.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (!rec.empty())
+            PT_HIP(hipMemcpy(c->rec, rec.data(), rec.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    // couplings: pack on the host, one sample at a time
+    {
+        std::vector<float> buf;
+        for (int s = 0; s < P.S; ++s) {
+            const int L = P.L[s];
+            buf.assign(static_cast<size_t>(54) * L * L * L, 0.0f);
+            pack_couplings(L, d->couplings[s], buf.data());
+            PT_HIP(hipMemcpy(c->cpl + P.cpl_base[s], buf.data(), buf.size() * sizeof(float),
+                             hipMemcpyHostToDevice));
+        }
+    }
+    // lattice classes (same L and T): one launch per class per half-sweep
+    {
+        std::map<std::pair<int, int>, std::vector<int>> groups;
+        for (int s = 0; s < P.S; ++s) groups[{P.L[s], P.T[s]}].push_back(s);
+        int *dsamp = reinterpret_cast<int *>(w + P.off_classes);
+        int at = 0;
+        for (auto &g : groups) {
+            LatticeClass k;
+            k.L = g.first.first;
+            k.T = g.first.second;
+            k.C = P.R * k.T;
+            const int H = k.L * k.L * k.L / 2;
+            k.n_site_blocks = (H + kSweepBlock - 1) / kSweepBlock;
+            k.G = choose_group(H, k.C, static_cast<int>(g.second.size()));
+            k.samples = g.second;
+            k.d_samples = dsamp + at;
+            PT_HIP(hipMemcpy(k.d_samples, g.second.data(), g.second.size() * sizeof(int),
+                             hipMemcpyHostToDevice));
+            at += static_cast<int>(g.second.size());
+            c->classes.push_back(k);
+        }
+    }
+    // hot start, then energies
+    for (int s = 0; s < P.S; ++s)
+        PT_HIP(launch_init_spins(c->spins, P.spin_base[s], P.L[s], P.R * P.T[s], P.T[s], s,
+                                 static_cast<uint32_t>(c->seed),
+                                 static_cast<uint32_t>(c->seed >> 32), st));
+    {
+        pt_status e = refresh_energies(c);
+        if (e != PT_OK) return e;
+    }
+    PT_HIP(hipStreamSynchronize(st));
+    *out = c;
+    c = nullptr;  // disarm the guard
+    return PT_OK;
+}
+
+pt_status pt_init(pt_ctx **ctx, int L, const float *couplings, const double *temps, int n_temps,
+                  int n_replicas, uint64_t seed)
+{
+    pt_batch_desc d{};
+    d.n_samples = 1;
+    d.L = &L;
+    d.n_temps = &n_temps;
+    d.temps = &temps;
+    d.couplings = &couplings;
+    d.n_replicas = n_replicas;
+    d.seed = seed;
+    return pt_init_batch(ctx, &d);
+}
+
+pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (n_hb < 0 || n_or < 0) return fail(PT_EINVAL, "n_hb and n_or must be >= 0");
+    const int total = n_hb + n_or;
+    for (int n = 0; n < total; ++n) {
+        const int kind = n < n_hb ? kHeatbath : kOverrelax;
+        const bool last = n == total - 1;
+        if ((st = half_sweep_all(c, kind, 0, false)) != PT_OK) return st;
+        if ((st = half_sweep_all(c, kind, 1, last)) != PT_OK) return st;
+        if (kind == kHeatbath) c->hb_sweeps += 1;
+    }
+    return PT_OK;
+}
+
+pt_status pt_swap(pt_ctx *c)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    SwapParams p{};
+    p.perm = c->perm;
+    p.slot_of = c->slot_of;
+    p.beta_of = c->beta_of;
+    p.E = c->E;
+    p.betas = c->betas;
+    p.chain_base = c->d_chain_base;
+    p.perm_base = c->d_perm_base;
+    p.beta_base = c->d_beta_base;
+    p.n_temps = c->d_T;
+    p.n_samples = c->plan.S;
+    p.R = c->plan.R;
+    p.pass = static_cast<uint32_t>(c->pt_passes);
+    p.key0 = static_cast<uint32_t>(c->seed);
+    p.key1 = static_cast<uint32_t>(c->seed >> 32);
+    PT_HIP(launch_swap(p, c->stream));
+    c->pt_passes += 1;
+    return PT_OK;
+}
+
+pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t *n_out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (what & ~static_cast<unsigned>(PT_M_ALL)) return fail(PT_EINVAL, "unknown measurement bits");
+    const Plan &P = c->plan;
+    if ((what & (PT_M_OVERLAP | PT_M_CHIRAL)) && P.R < 2)
+        return fail(PT_ESTATE, "overlap and chirality need n_replicas >= 2");
+    if (n_out) *n_out = static_cast<size_t>(P.n_records);
+    if (P.n_records == 0) return PT_OK;
+    if (!out) return fail(PT_EINVAL, "output buffer is NULL");
+    if (cap < static_cast<size_t>(P.n_records))
+        return fail(PT_ENOMEM, "output holds " + std::to_string(cap) + " records, " +
+                                   std::to_string(P.n_records) + " needed");
+    MeasParams m{};
+    m.spins = c->spins;
+    m.cpl = c->cpl;
+    m.rec = c->rec;
+    m.perm = c->perm;
+    m.perm_base = c->d_perm_base;
+    m.n_temps = c->d_T;
+    m.L = c->d_L;
+    m.chain_base = c->d_chain_base;
+    m.twid_base = c->d_twid_base;
+    m.spin_base = c->d_spin_base;
+    m.cpl_base = c->d_cpl_base;
+    m.twid = c->twid;
+    m.E = c->E;
+    m.betas = c->betas;
+    m.beta_base = c->d_beta_base;
+    m.part = c->mpart;
+    m.Lmax = P.Lmax;
+    m.n_records = P.n_records;
+    m.what = what;
+    m.out = c->meas;
+    PT_HIP(launch_measure(m, c->stream));
+    PT_HIP(hipMemcpyAsync(out, c->meas, sizeof(pt_meas) * P.n_records, hipMemcpyDeviceToHost,
+                          c->stream));
+    PT_HIP(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+static pt_status chain_of(pt_ctx *c, int sample, int rep, int tslot, int *chain_local)
+{
+    const Plan &P = c->plan;
+    if (sample < 0 || sample >= P.S) return fail(PT_EINVAL, "sample out of range");
+    if (rep < 0 || rep >= P.R) return fail(PT_EINVAL, "replica out of range");
+    if (tslot < 0 || tslot >= P.T[sample]) return fail(PT_EINVAL, "slot out of range");
+    int j = 0;
+    PT_HIP(hipMemcpyAsync(&j, c->perm + P.perm_base[sample] + rep * P.T[sample] + tslot, sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    PT_HIP(hipStreamSynchronize(c->stream));
+    *chain_local = rep * P.T[sample] + j;
+    return PT_OK;
+}
+
+pt_status pt_get_spins(pt_ctx *c, int sample, int rep, int tslot, float *out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!out) return fail(PT_EINVAL, "output is NULL");
+    int j;
+    if ((st = chain_of(c, sample, rep, tslot, &j)) != PT_OK) return st;
+    const int L = c->plan.L[sample], N = L * L * L, H = N / 2, Lh = L / 2;
+    std::vector<float> buf(3 * static_cast<size_t>(N));
+    PT_HIP(hipMemcpyAsync(buf.data(), c->spins + c->plan.spin_base[sample] + static_cast<int64_t>(j) * 3 * N,
+                          buf.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    PT_HIP(hipStreamSynchronize(c->stream));
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int i = x + L * (y + L * z), col = (x + y + z) & 1;
+                const int p = (x >> 1) + Lh * (y + L * z);
+                for (int a = 0; a < 3; ++a) out[3 * i + a] = buf[(col * 3 + a) * static_cast<size_t>(H) + p];
+            }
+    return PT_OK;
+}
+
+pt_status pt_set_spins(pt_ctx *c, int sample, int rep, int tslot, const float *in)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!in) return fail(PT_EINVAL, "input is NULL");
+    int j;
+    if ((st = chain_of(c, sample, rep, tslot, &j)) != PT_OK) return st;
+    const int L = c->plan.L[sample], N = L * L * L, H = N / 2, Lh = L / 2;
+    std::vector<float> buf(3 * static_cast<size_t>(N));
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int i = x + L * (y + L * z), col = (x + y + z) & 1;
+                const int p = (x >> 1) + Lh * (y + L * z);
+                for (int a = 0; a < 3; ++a) buf[(col * 3 + a) * static_cast<size_t>(H) + p] = in[3 * i + a];
+            }
+    PT_HIP(hipMemcpyAsync(c->spins + c->plan.spin_base[sample] + static_cast<int64_t>(j) * 3 * N, buf.data(),
+                          buf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    if ((st = refresh_energies(c)) != PT_OK) return st;
+    PT_HIP(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+pt_status pt_get_perm(pt_ctx *c, int sample, int rep, int32_t *out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    const Plan &P = c->plan;
+    if (!out) return fail(PT_EINVAL, "output is NULL");
+    if (sample < 0 || sample >= P.S) return fail(PT_EINVAL, "sample out of range");
+    if (rep < 0 || rep >= P.R) return fail(PT_EINVAL, "replica out of range");
+    PT_HIP(hipMemcpyAsync(out, c->perm + P.perm_base[sample] + rep * P.T[sample], sizeof(int) * P.T[sample],
+                          hipMemcpyDeviceToHost, c->stream));
+    PT_HIP(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+pt_status pt_get_energy(pt_ctx *c, double *out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!out) return fail(PT_EINVAL, "output is NULL");
+    const Plan &P = c->plan;
+    std::vector<double> E(P.n_chains);
+    std::vector<int> perm(P.total_perm);
+    PT_HIP(hipMemcpyAsync(E.data(), c->E, E.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PT_HIP(hipMemcpyAsync(perm.data(), c->perm, perm.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    PT_HIP(hipStreamSynchronize(c->stream));
+    size_t o = 0;
+    for (int s = 0; s < P.S; ++s)
+        for (int r = 0; r < P.R; ++r)
+            for (int k = 0; k < P.T[s]; ++k) {
+                const int j = perm[P.perm_base[s] + r * P.T[s] + k];
+                out[o++] = E[P.chain_base[s] + r * P.T[s] + j];
+            }
+    return PT_OK;
+}
+
+pt_status pt_get_counters(pt_ctx *c, uint64_t *hb, uint64_t *pt)
+{
+    if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
+    if (hb) *hb = c->hb_sweeps;
+    if (pt) *pt = c->pt_passes;
+    return PT_OK;
+}
+
+pt_status pt_set_stream(pt_ctx *c, void *stream)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if ((st = drain_events(c)) != PT_OK) return st;
+    c->stream = static_cast<hipStream_t>(stream);
+    return PT_OK;
+}
+
+pt_status pt_sync(pt_ctx *c)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    PT_HIP(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+pt_status pt_profile(pt_ctx *c, int enable)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if ((st = drain_events(c)) != PT_OK) return st;
+    c->profiling = enable != 0;
+    c->prof_launches[0] = c->prof_launches[1] = 0;
+    c->prof_ms[0] = c->prof_ms[1] = 0.0;
+    return PT_OK;
+}
+
+pt_status pt_kernel_time(pt_ctx *c, int kind, uint64_t *launches, double *ms)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (kind != PT_K_OVERRELAX && kind != PT_K_HEATBATH) return fail(PT_EINVAL, "unknown kernel kind");
+    if ((st = drain_events(c)) != PT_OK) return st;
+    if (launches) *launches = c->prof_launches[kind];
+    if (ms) *ms = c->prof_ms[kind];
+    return PT_OK;
+}
+
+void pt_free(pt_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &pe : c->pending) c->free_events.push_back(pe.second);
+    for (auto &e : c->free_events) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+// sweep.hip -- checkerboard half-sweep kernels (heat-bath, overrelaxation),
+// fused energy partials, energy finalisation and the hot start.
+//
+// Mapping: one lane = one site of the active colour; a workgroup owns 256
+// consecutive packed sites of one sample and a group of G chains of that
+// sample.  The 54 coupling values of the lane's site (six 3x3 matrices, see
+// kernels.hpp) are loaded once into registers and reused for every chain of
+// the group, so coupling traffic is divided by G; spins stream through
+// coalesced component rows.  Same-colour sites share no bond (appendix A.1),
+// so all lanes update independently and the result does not depend on the
+// schedule.
+#include "kernels.hpp"
+#include "philox.hpp"
+
+namespace ptsg {
+
+namespace {
+
+struct Nbr {
+    int idx[6];  // packed indices in the other colour: +x, -x, +y, -y, +z, -z
+    int site;    // canonical site index x + L*(y + L*z)
+};
+
+__device__ __forceinline__ Nbr neighbours(int p, int L, int colour)
+{
+    const int Lh = L >> 1;
+    const int xh = p % Lh;
+    const int row = p / Lh;         // y + L*z
+    const int y = row % L;
+    const int z = row / L;
+    const int par = (colour + y + z) & 1;   // parity of x
+    const int x = 2 * xh + par;
+    const int rb = p - xh;
+    Nbr n;
+    // x +- 1 lands in the other colour at packed x index xh (+1 or -1)
+    n.idx[0] = rb + (par ? (xh + 1 == Lh ? 0 : xh + 1) : xh);
+    n.idx[1] = rb + (par ? xh : (xh == 0 ? Lh - 1 : xh - 1));
+    const int dy = Lh, dz = Lh * L;
+    n.idx[2] = p + (y == L - 1 ? -(L - 1) * dy : dy);
+    n.idx[3] = p + (y == 0 ? (L - 1) * dy : -dy);
+    n.idx[4] = p + (z == L - 1 ? -(L - 1) * dz : dz);
+    n.idx[5] = p + (z == 0 ? (L - 1) * dz : -dz);
+    n.site = x + L * row;
+    return n;
+}
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Overrelaxation (appendix A.1): reflect about h, keep s.h; renormalise.
+__device__ __forceinline__ void overrelax(float &sx, float &sy, float &sz,
+                                          float hx, float hy, float hz)
+{
+    const float q = hx * hx + hy * hy + hz * hz;
+    if (q > 0.0f) {
+        const float f = 2.0f * (hx * sx + hy * sy + hz * sz) * rcp(q);
+        sx = f * hx - sx;
+        sy = f * hy - sy;
+        sz = f * hz - sz;
+        const float r = rsq(sx * sx + sy * sy + sz * sz);
+        sx *= r; sy *= r; sz *= r;
+    }
+}
+
+// Heat-bath (appendix A.1): draw s from exp(beta s.h) on the sphere.
+// c = cos(theta) about n = h/|h| has density ~ exp(X c), X = beta|h|;
+// inverting the upper tail of its CDF with a uniform v gives
+// t = 1 - c = -log1p(v expm1(-2X)) / X (flat law t = 2v below X = 2^-60).
+// The azimuth 2 pi u2 is measured in the branch-free orthonormal frame of
+// Duff et al. (JCGT 6(1), 2017) around n.
+__device__ __forceinline__ void heatbath(float &sx, float &sy, float &sz,
+                                         float hx, float hy, float hz,
+                                         float beta, float v, float u2)
+{
+    const float hn = sqrtf(hx * hx + hy * hy + hz * hz);
+    const float X = beta * hn;
+    float nx, ny, nz, t;
+    if (X < 0x1p-60f) {
+        nx = 0.0f; ny = 0.0f; nz = 1.0f;
+        t = 2.0f * v;
+    } else {
+        const float ih = 1.0f / hn;
+        nx = hx * ih; ny = hy * ih; nz = hz * ih;
+        t = -log1pf(v * expm1f(-2.0f * X)) / X;
+    }
+    const float ct = 1.0f - t;
+    const float st = sqrtf(fmaxf(t * (2.0f - t), 0.0f));
+    float sp, cp;
+    sincospif(2.0f * u2, &sp, &cp);
+    const float sg = copysignf(1.0f, nz);
+    const float a = -1.0f / (sg + nz);
+    const float b = nx * ny * a;
+    const float b1x = 1.0f + sg * nx * nx * a, b1y = sg * b, b1z = -sg * nx;
+    const float b2x = b, b2y = sg + ny * ny * a, b2z = -ny;
+    sx = ct * nx + st * (cp * b1x + sp * b2x);
+    sy = ct * ny + st * (cp * b1y + sp * b2y);
+    sz = ct * nz + st * (cp * b1z + sp * b2z);
+    const float r = rsq(sx * sx + sy * sy + sz * sz);
+    sx *= r; sy *= r; sz *= r;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int KIND, bool ENERGY>
+__global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
+{
+    const int s = P.samples[blockIdx.z];
+    const int p = blockIdx.x * kSweepBlock + threadIdx.x;
+    const bool active = p < P.H;
+    const int pc = active ? p : 0;
+    const int c = P.colour;
+    const Nbr nb = neighbours(pc, P.L, c);
+    const int H = P.H;
+
+    float A[54];
+    {
+        const float *cp = P.cpl + P.cpl_base[s] + static_cast<int64_t>(c) * 54 * H + pc;
+#pragma unroll
+        for (int m = 0; m < 54; ++m) A[m] = cp[static_cast<int64_t>(m) * H];
+    }
+
+    const int j0 = blockIdx.y * P.G;
+    const int j1 = min(j0 + P.G, P.C);
+    const int cb = P.chain_base[s];
+    __shared__ double e_wave[kSweepBlock / 64][kMaxGroup];
+
+    for (int j = j0; j < j1; ++j) {
+        float *base = P.spins + P.spin_base[s] + static_cast<int64_t>(j) * 6 * H;
+        const float *oth = base + (1 - c) * 3 * H;
+        float *own = base + c * 3 * H;
+        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+#pragma unroll
+        for (int n = 0; n < 6; ++n) {
+            const float vx = oth[nb.idx[n]];
+            const float vy = oth[H + nb.idx[n]];
+            const float vz = oth[2 * H + nb.idx[n]];
+            const float *a = A + n * 9;
+            hx += a[0] * vx + a[1] * vy + a[2] * vz;
+            hy += a[3] * vx + a[4] * vy + a[5] * vz;
+            hz += a[6] * vx + a[7] * vy + a[8] * vz;
+        }
+        float sx, sy, sz;
+        if constexpr (KIND == kHeatbath) {
+            const int chain = cb + j;
+            const int rep = j / P.T;
+            const uint4 w = philox10(
+                make_uint4(static_cast<uint32_t>(nb.site), P.hb_sweep, static_cast<uint32_t>(s),
+                           ctr_word3(0u, static_cast<uint32_t>(P.slot_of[chain]),
+                                     static_cast<uint32_t>(rep))),
+                P.key0, P.key1);
+            heatbath(sx, sy, sz, hx, hy, hz, P.beta_of[chain], unit23(w.x), unit23(w.y));
+        } else {
+            sx = own[pc];
+            sy = own[H + pc];
+            sz = own[2 * H + pc];
+            if constexpr (KIND == kOverrelax) overrelax(sx, sy, sz, hx, hy, hz);
+        }
+        if (KIND != kEnergyOnly && active) {
+            own[pc] = sx;
+            own[H + pc] = sy;
+            own[2 * H + pc] = sz;
+        }
+        if constexpr (ENERGY) {
+            // every bond has exactly one end of colour 1: E = -sum_{colour 1} s.h
+            double e = active ? static_cast<double>(sx) * hx + static_cast<double>(sy) * hy +
+                                    static_cast<double>(sz) * hz
+                              : 0.0;
+            e = wave_sum(e);
+            if ((threadIdx.x & 63) == 0) e_wave[threadIdx.x >> 6][j - j0] = e;
+        }
+    }
+    if constexpr (ENERGY) {
+        __syncthreads();
+        const int nj = j1 - j0;
+        for (int t = threadIdx.x; t < nj; t += kSweepBlock) {
+            double e = 0.0;
+#pragma unroll
+            for (int w = 0; w < kSweepBlock / 64; ++w) e += e_wave[w][t];
+            P.e_part[static_cast<int64_t>(cb + j0 + t) * P.e_stride + blockIdx.x] = e;
+        }
+    }
+}
+
+// E[chain] = -(sum of its partials), summed in block order.
+__global__ void energy_finalize_kernel(EnergyParams P)
+{
+    const int s = P.samples[blockIdx.y];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= P.C) return;
+    const int chain = P.chain_base[s] + j;
+    const double *e = P.e_part + static_cast<int64_t>(chain) * P.e_stride;
+    double acc = 0.0;
+    for (int b = 0; b < P.n_blocks; ++b) acc += e[b];
+    P.E[chain] = -acc;
+}
+
+// Hot start: z = 1 - 2u1 uniform on [-1,1], azimuth 2 pi u2 (uniform law on
+// the sphere), counter (site, 0, sample, tag 2 | start slot j | replica).
+__global__ void init_spins_kernel(float *spins, int L, int H, int T, int sample,
+                                  uint32_t key0, uint32_t key1)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= H) return;
+    const int colour = blockIdx.y;
+    const int chain = blockIdx.z;  // rep*T + j
+    const Nbr nb = neighbours(p, L, colour);
+    const uint4 w = philox10(make_uint4(static_cast<uint32_t>(nb.site), 0u,
+                                        static_cast<uint32_t>(sample),
+                                        ctr_word3(2u, static_cast<uint32_t>(chain % T),
+                                                  static_cast<uint32_t>(chain / T))),
+                             key0, key1);
+    const float z = 1.0f - 2.0f * unit23(w.x);
+    float sp, cp;
+    sincospif(2.0f * unit23(w.y), &sp, &cp);
+    const float r = sqrtf(fmaxf(1.0f - z * z, 0.0f));
+    float *o = spins + static_cast<int64_t>(chain) * 6 * H + colour * 3 * H;
+    o[p] = r * cp;
+    o[H + p] = r * sp;
+    o[2 * H + p] = z;
+}
+
+}  // namespace
+
+hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_samples,
+                             hipStream_t st)
+{
+    const dim3 grid((p.H + kSweepBlock - 1) / kSweepBlock, (p.C + p.G - 1) / p.G, n_samples);
+    const dim3 block(kSweepBlock);
+    if (kind == kOverrelax) {
+        if (energy) hipLaunchKernelGGL((half_sweep_kernel<kOverrelax, true>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((half_sweep_kernel<kOverrelax, false>), grid, block, 0, st, p);
+    } else if (kind == kHeatbath) {
+        if (energy) hipLaunchKernelGGL((half_sweep_kernel<kHeatbath, true>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((half_sweep_kernel<kHeatbath, false>), grid, block, 0, st, p);
+    } else {
+        hipLaunchKernelGGL((half_sweep_kernel<kEnergyOnly, true>), grid, block, 0, st, p);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st)
+{
+    const dim3 grid((p.C + 63) / 64, n_samples);
+    hipLaunchKernelGGL(energy_finalize_kernel, grid, dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_spins(float *spins, int64_t spin_base, int L, int C, int T, int sample,
+                             uint32_t key0, uint32_t key1, hipStream_t st)
+{
+    const int H = L * L * L / 2;
+    const dim3 grid((H + 255) / 256, 2, C);
+    hipLaunchKernelGGL(init_spins_kernel, grid, dim3(256), 0, st, spins + spin_base, L, H, T,
+                       sample, key0, key1);
+    return hipGetLastError();
+}
+
+}  // namespace ptsg

@@ -1,0 +1,87 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point
+include/ptsg.h declares, and rejects invalid arguments before touching a
+device (no kernel is launched here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1309_1599_amd import inputs, ptsg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptsg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ptsg.LIB_PATH):
+        from paper_1309_1599_amd import build
+        build.build()
+    return ptsg.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "pt_init" in names and "pt_measure" in names
+    assert sorted(ptsg.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_meas_record_layout():
+    assert ptsg.MEAS_DTYPE.itemsize == 744
+    assert ptsg.MEAS_DTYPE.fields["beta"][1] == 16
+    assert ptsg.MEAS_DTYPE.fields["sd2_b"][1] == 744 - 8
+
+
+def test_workspace_size_accounts_for_state(lib):
+    L, T, R = 16, 4, 2
+    cpl = [inputs.gaussian_couplings(L, 1)]
+    n = ptsg.pt_workspace_size([L], cpl, [inputs.geometric_temps(0.5, 1.5, T)], R)
+    N = L ** 3
+    spins = 4 * 3 * N * T * R
+    couplings = 4 * 54 * N
+    assert n >= spins + couplings
+    assert n < 2 * (spins + couplings) + (1 << 20)
+
+
+@pytest.mark.parametrize("L,temps,R,why", [
+    (5, [1.0, 2.0], 2, "L must be even"),
+    (2, [1.0, 2.0], 2, "L must be even"),
+    (8, [2.0, 1.0], 2, "strictly ascending"),
+    (8, [1.0, 1.0], 2, "strictly ascending"),
+    (8, [-1.0, 1.0], 2, "> 0"),
+    (8, [1.0, 2.0], 0, "n_replicas"),
+    (8, [], 2, "n_temps"),
+])
+def test_invalid_arguments_rejected(lib, L, temps, R, why):
+    cpl = np.zeros((3, L ** 3, 3, 3), np.float32)
+    assert ptsg.pt_workspace_size([L], [cpl], [temps], R) == 0
+    with pytest.raises(ptsg.PtError) as e:
+        ptsg.pt_init(L, cpl, temps, R, 1)
+    assert e.value.status == ptsg.PT_EINVAL
+    assert why in str(e.value)
+
+
+def test_non_finite_coupling_rejected(lib):
+    L = 4
+    cpl = np.zeros((3, L ** 3, 3, 3), np.float32)
+    cpl[1, 7, 2, 0] = np.nan
+    with pytest.raises(ptsg.PtError) as e:
+        ptsg.pt_init(L, cpl, [1.0], 1, 1)
+    assert e.value.status == ptsg.PT_EINVAL and "non-finite" in str(e.value)
+
+
+def test_null_context_is_state_error(lib):
+    assert lib.pt_step(None, 1, 1) == ptsg.PT_ESTATE
+    assert lib.pt_swap(None) == ptsg.PT_ESTATE
+    assert "pt_init" in ptsg.pt_last_error()
+    lib.pt_free(None)  # no-op
