@@ -65,7 +65,12 @@ __device__ __forceinline__ void overrelax(float &sx, float &sy, float &sz,
 // Heat-bath (appendix A.1): draw s from exp(beta s.h) on the sphere.
 // c = cos(theta) about n = h/|h| has density ~ exp(X c), X = beta|h|;
 // inverting the upper tail of its CDF with a uniform v gives
-// t = 1 - c = -log1p(v expm1(-2X)) / X (flat law t = 2v below X = 2^-60).
+//   t = 1 - c = -log(1 + v expm1(-2X)) / X    (flat law t = 2v below 2^-60).
+// FP32 evaluation: the argument 1 + v expm1(-2X) equals (1-v) + v e^{-2X},
+// a sum of two positive terms (1-v is exact), which keeps its relative
+// accuracy where it is small; log1p is used where it is not.  The
+// complement p = 1 + c = log1p((1-v) expm1(2X)) / X is evaluated on its own
+// so that sin(theta) = sqrt(t p) stays accurate near both poles.
 // The azimuth 2 pi u2 is measured in the branch-free orthonormal frame of
 // Duff et al. (JCGT 6(1), 2017) around n.
 __device__ __forceinline__ void heatbath(float &sx, float &sy, float &sz,
@@ -74,17 +79,21 @@ __device__ __forceinline__ void heatbath(float &sx, float &sy, float &sz,
 {
     const float hn = sqrtf(hx * hx + hy * hy + hz * hz);
     const float X = beta * hn;
-    float nx, ny, nz, t;
+    const float u = 1.0f - v;  // exact: v has 24 significant bits at most
+    float nx, ny, nz, t, p;
     if (X < 0x1p-60f) {
         nx = 0.0f; ny = 0.0f; nz = 1.0f;
         t = 2.0f * v;
+        p = 2.0f * u;
     } else {
         const float ih = 1.0f / hn;
         nx = hx * ih; ny = hy * ih; nz = hz * ih;
-        t = -log1pf(v * expm1f(-2.0f * X)) / X;
+        const float w = v * expm1f(-2.0f * X);
+        t = -(w > -0.5f ? log1pf(w) : logf(u + v * expf(-2.0f * X))) / X;
+        p = X <= 40.0f ? log1pf(u * expm1f(2.0f * X)) / X : 2.0f - t;
     }
-    const float ct = 1.0f - t;
-    const float st = sqrtf(fmaxf(t * (2.0f - t), 0.0f));
+    const float ct = t <= 1.0f ? 1.0f - t : p - 1.0f;
+    const float st = sqrtf(fmaxf(t * p, 0.0f));
     float sp, cp;
     sincospif(2.0f * u2, &sp, &cp);
     const float sg = copysignf(1.0f, nz);

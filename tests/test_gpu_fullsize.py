@@ -1,0 +1,133 @@
+"""Parity at the benchmark's full size and launch configuration (L = 64,
+8 samples x 32 temperatures x 4 replicas), on sampled outputs the oracle
+computes one by one.
+
+Within a half-sweep every site of the active colour is updated from its
+neighbours of the other colour only, so a site's new value is a function of
+(pre-sweep state of the other colour, its own old value).  For colour-0
+sites the neighbours are the pre-sweep state; for colour-1 sites they are
+the post-sweep colour-0 values.  The oracle recomputes sampled sites from
+exactly those inputs, which checks the kernel without any trajectory
+divergence.  Energies, the tempering pass and measurement records are
+checked on whole chains.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_helpers import TOL, H_C, colours, energy_scale
+from paper_1309_1599_amd import inputs, ptsg
+
+pytestmark = pytest.mark.gpu
+
+PRESET = "L64x8"
+CHAINS = [(0, 0, 0), (3, 2, 17), (7, 3, 31)]  # (sample, replica, slot)
+N_SITES = 1500
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    assert torch.cuda.is_available()
+    Ls, cpl, temps, R, seed = inputs.preset_inputs(PRESET)
+    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed)
+    yield dict(ctx=ctx, L=Ls[0], cpl=cpl, temps=temps, R=R, seed=seed)
+    ptsg.pt_free(ctx)
+
+
+def _check_sweep(b, kind):
+    ctx, L = b["ctx"], b["L"]
+    N = L ** 3
+    col = colours(L)
+    rng = np.random.default_rng(5 + kind)
+    hb = ptsg.pt_get_counters(ctx)[0]
+    before = {c: ptsg.pt_get_spins(ctx, *c) for c in CHAINS}
+    ptsg.pt_step(ctx, 1 if kind == 1 else 0, 0 if kind == 1 else 1)
+    E = ptsg.pt_get_energy(ctx)
+    key = [b["seed"] & 0xFFFFFFFF, b["seed"] >> 32]
+    worst = 0.0
+    for (s, r, k) in CHAINS:
+        M = b["cpl"][s].astype(np.float64)
+        after = ptsg.pt_get_spins(ctx, s, r, k)
+        mixed = np.where(col[:, None] == 0, after, before[(s, r, k)]).astype(np.float64)
+        pre0 = before[(s, r, k)].astype(np.float64)
+        beta = 1.0 / b["temps"][s][k]
+        for i in rng.choice(N, N_SITES, replace=False):
+            state = pre0 if col[i] == 0 else mixed
+            h = O.local_field(L, M, state, int(i))
+            if kind == 0:
+                ref = O.overrelax_spin(h, state[i])
+            else:
+                w = O.philox(key, [int(i), hb, s, O.ctr3(O.TAG_HB, k, r)])
+                ref = O.heatbath_spin(h, beta, O.u23(w[0]), O.u23(w[1]))
+            d = np.linalg.norm(after[i] - ref)
+            bound = TOL * max(1.0, H_C / np.linalg.norm(h))
+            assert d <= bound, (kind, s, r, k, int(i), d, np.linalg.norm(h))
+            worst = max(worst, d)
+        Eref = O.energy(L, M, after.astype(np.float64))
+        assert abs(E[s][r, k] - Eref) <= 1e-6 * energy_scale(L, M, after), (s, r, k)
+    return worst
+
+
+def test_fullsize_heatbath_sweep(big):
+    _check_sweep(big, 1)
+
+
+def test_fullsize_overrelaxation_sweep(big):
+    _check_sweep(big, 0)
+
+
+def test_fullsize_tempering(big):
+    ctx = big["ctx"]
+    E = ptsg.pt_get_energy(ctx)
+    R = big["R"]
+    perms = {(s, r): ptsg.pt_get_perm(ctx, s, r) for s in range(ctx.n_samples) for r in range(R)}
+    p = ptsg.pt_get_counters(ctx)[1]
+    ptsg.pt_swap(ctx)
+    for (s, r), perm in perms.items():
+        T = len(perm)
+        Ech = np.empty(T)
+        Ech[perm] = E[s][r]
+        ref = perm.copy()
+        O.pt_pass(1.0 / big["temps"][s], Ech, ref, big["seed"], p, s, r)
+        np.testing.assert_array_equal(ptsg.pt_get_perm(ctx, s, r), ref, err_msg=f"{s},{r}")
+
+
+def test_fullsize_measure_sampled_records(big):
+    ctx, L = big["ctx"], big["L"]
+    recs = ptsg.pt_measure(ctx, ptsg.PT_M_ALL)
+    assert len(recs) == ctx.n_records == 8 * 32 * 6
+    for n in (0, 777, len(recs) - 1):
+        g = recs[n]
+        s, k, a, bb = int(g["sample"]), int(g["tslot"]), int(g["rep_a"]), int(g["rep_b"])
+        sa = ptsg.pt_get_spins(ctx, s, a, k).astype(np.float64)
+        sb = ptsg.pt_get_spins(ctx, s, bb, k).astype(np.float64)
+        ref = O.overlaps(L, sa, sb)
+        for key in ("q0", "qk_re", "qk_im", "cg0", "cgk_re", "cgk_im"):
+            np.testing.assert_allclose(g[key], ref[key], rtol=0, atol=1e-12, err_msg=key)
+        M = big["cpl"][s].astype(np.float64)
+        sd1, sd2 = O.sd_sums(L, M, sa)
+        assert abs(g["sd1_a"] - sd1) <= 1e-12 * abs(sd1) and abs(g["sd2_a"] - sd2) <= 1e-12 * abs(sd2)
+
+
+def test_largest_lattice_single_chain():
+    """L = 128 (N = 2^21), the largest size exercised: indexing beyond the
+    presets' range, sampled sites of one overrelaxation sweep."""
+    L, seed = 128, 901
+    cpl = inputs.gaussian_couplings(L, seed)
+    ctx = ptsg.pt_init_batch([L], [cpl], [[1.0]], 1, seed)
+    before = ptsg.pt_get_spins(ctx, 0, 0, 0)
+    ptsg.pt_step(ctx, 0, 1)
+    after = ptsg.pt_get_spins(ctx, 0, 0, 0)
+    col = colours(L)
+    M = cpl.astype(np.float64)
+    mixed = np.where(col[:, None] == 0, after, before).astype(np.float64)
+    rng = np.random.default_rng(3)
+    # include the corners and faces of the periodic box
+    sites = list(rng.choice(L ** 3, 800, replace=False)) + [0, L - 1, L * L - 1, L ** 3 - 1]
+    for i in sites:
+        state = before.astype(np.float64) if col[i] == 0 else mixed
+        h = O.local_field(L, M, state, int(i))
+        ref = O.overrelax_spin(h, state[i])
+        assert np.linalg.norm(after[i] - ref) <= TOL * max(1.0, H_C / np.linalg.norm(h))
+    ptsg.pt_free(ctx)
