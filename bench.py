@@ -52,7 +52,7 @@ def pmc_traffic(expected_hash):
     return float(b.group(1))
 
 
-def cpu_baseline(L, cpl, temps, seed, n_chains=32, n_or=8):
+def cpu_baseline(L, cpl, temps, seed, n_chains=64, n_or=12):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
     the same workload: n_chains chains of sample 0, one heat-bath sweep,
     n_or overrelaxation sweeps and one energy evaluation each; the step's
@@ -192,7 +192,7 @@ def main():
             "unit": "ps/SU",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"32 chains of sample 0 at L={L}: 1 heat-bath + 8 overrelaxation sweeps and one "
+            "sample": f"64 chains of sample 0 at L={L}: 1 heat-bath + 12 overrelaxation sweeps and one "
                       f"energy each ({spent:.1f} s), composed to the {n_hb} HB + {n_or} OR step",
         }
     print(json.dumps(result), flush=True)
