@@ -115,74 +115,166 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// Buffer-resource access: the chain's base address and size live in
+// SGPRs, each lane supplies a 32-bit byte offset, and the component stride
+// goes in the scalar offset, so addressing costs no vector ALU work.
+// Out-of-range offsets read as zero and drop stores (the size bound).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dwords (CDNA3/CDNA4)
+
+__device__ __forceinline__ Rsrc make_rsrc(const float *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0, static_cast<int>(bytes),
+                                             kRsrcWord3);
+}
+
+__device__ __forceinline__ float ld(Rsrc r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void st(Rsrc r, float v, unsigned voff, unsigned soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// The 21 spin values one lane reads per chain: the three components of
+// its own spin (overrelaxation only) and of its six other-colour neighbours.
+struct Gather {
+    float o[3];
+    float n[6][3];
+};
+
+// Byte offsets of those values inside one chain's [2][3][H] block; the
+// component k adds k*4H (scalar).
+struct Offsets {
+    unsigned own;    // 4 * (c*3H + p)
+    unsigned n[6];   // 4 * ((1-c)*3H + neighbour index)
+};
+
+template <bool OWN>
+__device__ __forceinline__ void gather(Gather &g, Rsrc r, const Offsets &off, unsigned H4)
+{
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        g.n[n][0] = ld(r, off.n[n], 0);
+        g.n[n][1] = ld(r, off.n[n], H4);
+        g.n[n][2] = ld(r, off.n[n], 2 * H4);
+    }
+    if constexpr (OWN) {
+        g.o[0] = ld(r, off.own, 0);
+        g.o[1] = ld(r, off.own, H4);
+        g.o[2] = ld(r, off.own, 2 * H4);
+    }
+}
+
+// h = sum_n A_n s_n, then the update; returns s.h of the new spin (FP64)
+// for the energy partial.
+template <int KIND>
+__device__ __forceinline__ double update(const Gather &g, const float (&A)[54], Rsrc r,
+                                         const Offsets &off, unsigned H4, bool active,
+                                         uint32_t site, uint32_t sample, uint32_t ctr3,
+                                         uint32_t hb_sweep, uint32_t key0, uint32_t key1, float beta)
+{
+    // 54 chained multiply-adds
+    float h[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        h[a] = A[a * 3] * g.n[0][0];
+        h[a] = fmaf(A[a * 3 + 1], g.n[0][1], h[a]);
+        h[a] = fmaf(A[a * 3 + 2], g.n[0][2], h[a]);
+    }
+#pragma unroll
+    for (int n = 1; n < 6; ++n)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) h[a] = fmaf(A[n * 9 + a * 3 + b], g.n[n][b], h[a]);
+    float sx, sy, sz;
+    if constexpr (KIND == kHeatbath) {
+        const uint4 w = philox10(make_uint4(site, hb_sweep, sample, ctr3), key0, key1);
+        heatbath(sx, sy, sz, h[0], h[1], h[2], beta, unit23(w.x), unit23(w.y));
+    } else {
+        sx = g.o[0]; sy = g.o[1]; sz = g.o[2];
+        if constexpr (KIND == kOverrelax) overrelax(sx, sy, sz, h[0], h[1], h[2]);
+    }
+    if (KIND != kEnergyOnly && active) {
+        st(r, sx, off.own, 0);
+        st(r, sy, off.own, H4);
+        st(r, sz, off.own, 2 * H4);
+    }
+    return static_cast<double>(sx) * h[0] + static_cast<double>(sy) * h[1] +
+           static_cast<double>(sz) * h[2];
+}
+
 template <int KIND, bool ENERGY>
 __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
 {
+    constexpr bool kOwn = KIND != kHeatbath;  // heat-bath ignores the old spin
     const int s = P.samples[blockIdx.z];
     const int p = blockIdx.x * kSweepBlock + threadIdx.x;
     const bool active = p < P.H;
     const int pc = active ? p : 0;
     const int c = P.colour;
+    const unsigned H = static_cast<unsigned>(P.H);
+    const unsigned H4 = 4u * H;
     const Nbr nb = neighbours(pc, P.L, c);
-    const int H = P.H;
+    Offsets off;
+    off.own = 4u * (static_cast<unsigned>(c) * 3u * H + static_cast<unsigned>(pc));
+#pragma unroll
+    for (int n = 0; n < 6; ++n)
+        off.n[n] = 4u * (static_cast<unsigned>(1 - c) * 3u * H + static_cast<unsigned>(nb.idx[n]));
 
     float A[54];
     {
-        const float *cp = P.cpl + P.cpl_base[s] + static_cast<int64_t>(c) * 54 * H + pc;
+        const Rsrc rc = make_rsrc(P.cpl + P.cpl_base[s] + static_cast<int64_t>(c) * 54 * H, 54u * H4);
+        const unsigned o = 4u * static_cast<unsigned>(pc);
 #pragma unroll
-        for (int m = 0; m < 54; ++m) A[m] = cp[static_cast<int64_t>(m) * H];
+        for (int m = 0; m < 54; ++m) A[m] = ld(rc, o, static_cast<unsigned>(m) * H4);
     }
 
     const int j0 = blockIdx.y * P.G;
     const int j1 = min(j0 + P.G, P.C);
     const int cb = P.chain_base[s];
+    const int64_t stride = 6 * static_cast<int64_t>(H);
+    const float *chain0 = P.spins + P.spin_base[s] + static_cast<int64_t>(j0) * stride;
+    const unsigned chain_bytes = 6u * H4;
     __shared__ double e_wave[kSweepBlock / 64][kMaxGroup];
 
-    for (int j = j0; j < j1; ++j) {
-        float *base = P.spins + P.spin_base[s] + static_cast<int64_t>(j) * 6 * H;
-        const float *oth = base + (1 - c) * 3 * H;
-        float *own = base + c * 3 * H;
-        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-#pragma unroll
-        for (int n = 0; n < 6; ++n) {
-            const float vx = oth[nb.idx[n]];
-            const float vy = oth[H + nb.idx[n]];
-            const float vz = oth[2 * H + nb.idx[n]];
-            const float *a = A + n * 9;
-            hx += a[0] * vx + a[1] * vy + a[2] * vz;
-            hy += a[3] * vx + a[4] * vy + a[5] * vz;
-            hz += a[6] * vx + a[7] * vy + a[8] * vz;
-        }
-        float sx, sy, sz;
+    auto rsrc_of = [&](int j) { return make_rsrc(chain0 + static_cast<int64_t>(j - j0) * stride, chain_bytes); };
+
+    auto process = [&](const Gather &g, int j) {
+        uint32_t ctr3 = 0;
+        float beta = 0.0f;
         if constexpr (KIND == kHeatbath) {
             const int chain = cb + j;
-            const int rep = j / P.T;
-            const uint4 w = philox10(
-                make_uint4(static_cast<uint32_t>(nb.site), P.hb_sweep, static_cast<uint32_t>(s),
-                           ctr_word3(0u, static_cast<uint32_t>(P.slot_of[chain]),
-                                     static_cast<uint32_t>(rep))),
-                P.key0, P.key1);
-            heatbath(sx, sy, sz, hx, hy, hz, P.beta_of[chain], unit23(w.x), unit23(w.y));
-        } else {
-            sx = own[pc];
-            sy = own[H + pc];
-            sz = own[2 * H + pc];
-            if constexpr (KIND == kOverrelax) overrelax(sx, sy, sz, hx, hy, hz);
+            ctr3 = ctr_word3(0u, static_cast<uint32_t>(P.slot_of[chain]),
+                             static_cast<uint32_t>(j / P.T));
+            beta = P.beta_of[chain];
         }
-        if (KIND != kEnergyOnly && active) {
-            own[pc] = sx;
-            own[H + pc] = sy;
-            own[2 * H + pc] = sz;
-        }
+        const double e = update<KIND>(g, A, rsrc_of(j), off, H4, active,
+                                      static_cast<uint32_t>(nb.site), static_cast<uint32_t>(s),
+                                      ctr3, P.hb_sweep, P.key0, P.key1, beta);
         if constexpr (ENERGY) {
             // every bond has exactly one end of colour 1: E = -sum_{colour 1} s.h
-            double e = active ? static_cast<double>(sx) * hx + static_cast<double>(sy) * hy +
-                                    static_cast<double>(sz) * hz
-                              : 0.0;
-            e = wave_sum(e);
-            if ((threadIdx.x & 63) == 0) e_wave[threadIdx.x >> 6][j - j0] = e;
+            const double w = wave_sum(active ? e : 0.0);
+            if ((threadIdx.x & 63) == 0) e_wave[threadIdx.x >> 6][j - j0] = w;
         }
+    };
+
+    // Software pipeline over the chains: the loads of chain j+1 are in
+    // flight while chain j is updated.
+    Gather ga, gb;
+    gather<kOwn>(ga, rsrc_of(j0), off, H4);
+    for (int j = j0; j < j1; j += 2) {
+        const bool has_b = j + 1 < j1;
+        if (has_b) gather<kOwn>(gb, rsrc_of(j + 1), off, H4);
+        process(ga, j);
+        if (!has_b) break;
+        if (j + 2 < j1) gather<kOwn>(ga, rsrc_of(j + 2), off, H4);
+        process(gb, j + 1);
     }
+
     if constexpr (ENERGY) {
         __syncthreads();
         const int nj = j1 - j0;
