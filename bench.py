@@ -25,7 +25,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "ps per spin update (all chains) & HBM roofline %, batched FP32 vs plain FP64"
-KERNEL_SOURCES = ["paper_1309_1599_amd/csrc/sweep.hip", "paper_1309_1599_amd/csrc/kernels.hpp",
+KERNEL_SOURCES = ["paper_1309_1599_amd/csrc/sweep.hip", "paper_1309_1599_amd/csrc/sweep_cl.hip",
+                  "paper_1309_1599_amd/csrc/spin_update.hpp", "paper_1309_1599_amd/csrc/kernels.hpp",
                   "paper_1309_1599_amd/csrc/philox.hpp"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "overrelax_half_sweep_L64x8_pmc.txt")
 
@@ -88,6 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--preset", default="L64x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mapping", choices=("auto", "site", "chain"), default="auto",
+                    help="sweep kernel mapping (auto: chain lanes when a sample has >= 48 chains)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path does not "
@@ -114,7 +117,10 @@ def main():
     b.copy_(a)
     del a, b
 
-    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed)
+    flags = {"auto": 0, "site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES}[args.mapping]
+    C_sample = R * len(temps[0])
+    mapping = args.mapping if args.mapping != "auto" else ("chain" if C_sample >= 48 and L <= 128 else "site")
+    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
     n_chains = ctx.n_chains
     N = L ** 3
     su_per_step = (n_hb + n_or) * n_chains * N
@@ -144,7 +150,9 @@ def main():
     ps_per_su = wall / (args.steps * su_per_step) * 1e12
     C = R * len(temps[0])
     bytes_per_su = 24.0 + 108.0 / C           # spin read + write, couplings shared by C chains
-    su_per_launch = n_chains * N // 2          # one half-sweep of every chain
+    # overrelaxation spin updates in the timed region, over all launches
+    or_su = args.steps * n_or * n_chains * N
+    su_per_launch = or_su / max(1, n_or_launch)
     avg_or_s = or_ms / max(1, n_or_launch) / 1e3
     achieved = bytes_per_su * su_per_launch / avg_or_s / 1e9
     traffic = pmc_traffic(kernel_hash())
@@ -168,16 +176,19 @@ def main():
                         f"{n_or} OR sweeps + PT pass" + (f", measurement every {every} steps" if every else ""),
             "L": L, "samples": len(Ls), "temperatures": len(temps[0]), "replicas": R,
             "spin_updates_per_step": su_per_step,
+            "mapping": mapping + " lanes",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "half_sweep_kernel<overrelax>",
+            "kernel": ("cl_half_sweep_kernel<overrelax>" if mapping == "chain"
+                       else "half_sweep_kernel<overrelax>"),
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4),
             "traffic": traffic,
             "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
+            "bytes_per_su": round(bytes_per_su, 4),
             "avg_launch_ms": round(avg_or_s * 1e3, 4),
             "launches": n_or_launch,
             "kernel_source_sha256": kernel_hash(),

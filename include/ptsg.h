@@ -109,7 +109,20 @@ typedef struct {
     void *stream;                  /* hipStream_t for all work; NULL = null stream */
     void *workspace;               /* caller device memory, or NULL: library allocates */
     size_t workspace_bytes;        /* size of `workspace` (>= pt_workspace_size) */
+    unsigned flags;                /* PT_F_* below; 0 = automatic choices */
 } pt_batch_desc;
+
+/* Kernel mapping of the sweeps (results are bit-identical in both):
+ * site lanes: one lane per site, a workgroup loops over the chains of a
+ *   sample with the site's couplings held in registers;
+ * chain lanes: one wave = 64 chains of a sample at one site, couplings in
+ *   scalar registers; each 64-chain group runs all sweeps of a step back to
+ *   back so that its working set stays in the 256 MB Infinity Cache.
+ * Automatic: chain lanes when a sample has >= 48 chains and L <= 128. */
+enum {
+    PT_F_SITE_LANES = 1u,
+    PT_F_CHAIN_LANES = 2u
+};
 
 /* One sample (the single-lattice form of the API).  Equivalent to
  * pt_init_batch with n_samples = 1, the null stream and library-owned

@@ -14,6 +14,11 @@
 //          from x-e_mu, so that  h_x = sum_n A_n s_{nbr_n(x)}.  The
 //          duplication (each bond stored twice) buys fully coalesced,
 //          gather-free coupling loads.
+//          (This is the site-lane layout, lanes = 1.  The chain-lane layout,
+//          lanes = 64, stores group g = j/64 of a sample as
+//          [colour][H][component][64], lane = j%64; see spin_index.)
+//  cpls    per sample, site-major canonical couplings [N][3][3][3]: the
+//          three forward bond matrices of site i are floats 27i .. 27i+26.
 //  chains  global chain id = chain_base[sample] + rep*T + j, j = start slot.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -24,11 +29,24 @@ namespace ptsg {
 constexpr int kSweepBlock = 256;   // threads per sweep workgroup (4 waves)
 constexpr int kMaxGroup = 128;     // chains per sweep workgroup (upper bound)
 constexpr int kMeasBlock = 256;
+constexpr int kClWaves = 4;        // chain-lane mapping: waves per workgroup
+constexpr int kClBlock = 64 * kClWaves;
+constexpr int kClSites = 16;       // consecutive packed sites per wave
 constexpr int kOverlapQ = 45;      // plane partials: Q(0), Q(kx), Q(ky) re/im, 9 each
 constexpr int kChiralQ = 19;       // kappa(0), kappa(kx), kappa(ky) re/im, 3 each; 4 SD sums
 constexpr int kPlaneQ = kOverlapQ + kChiralQ;
 
 enum SweepKind { kOverrelax = 0, kHeatbath = 1, kEnergyOnly = 2 };
+
+// Float index of component k of the site with packed index p (colour c) of
+// chain j of a sample whose spins start at `base`, in either layout.
+__host__ __device__ inline int64_t spin_index(int64_t base, int lanes, int64_t H, int j, int c, int k,
+                                             int64_t p)
+{
+    if (lanes == 1) return base + ((static_cast<int64_t>(j) * 2 + c) * 3 + k) * H + p;
+    const int g = j >> 6, l = j & 63;
+    return base + (((static_cast<int64_t>(g) * 2 + c) * H + p) * 3 + k) * 64 + l;
+}
 
 struct SweepParams {
     float *spins;
@@ -42,6 +60,26 @@ struct SweepParams {
     double *e_part;              // [global chain][e_stride] energy partials
     int e_stride;
     int L, H, C, G, T;           // lattice, N/2, chains/sample, chains/workgroup, slots
+    int n_tiles, per;            // site blocks per sample; blocks per XCD (grid = 8*per)
+    int colour;
+    uint32_t hb_sweep, key0, key1;
+};
+
+// Chain-lane mapping (one wave = 64 chains of one sample at one site).
+struct ClParams {
+    float *spins;
+    const float *cpls;           // site-major couplings [N][3][3][3] per sample
+    const int *items;            // [n_items][2]: (sample, chain group)
+    const int64_t *spin_base;
+    const int64_t *cpls_base;
+    const int *chain_base;
+    const int *slot_of;
+    const float *beta_of;
+    double *e_part;
+    int e_stride;
+    int L, H, C, T;
+    int split;                   // waves per packed row (divides L/2)
+    int n_tiles, per;            // workgroups of rows per item; per XCD (grid = 8*per)
     int colour;
     uint32_t hb_sweep, key0, key1;
 };
@@ -67,10 +105,11 @@ struct EnergyParams {
 
 struct MeasParams {
     const float *spins;
-    const float *cpl;
+    const float *cpls;           // site-major couplings
     const int *rec;              // [n_records][4]: sample, slot, rep_a, rep_b
     const int *perm, *perm_base, *n_temps, *L, *chain_base, *twid_base;
-    const int64_t *spin_base, *cpl_base;
+    const int64_t *spin_base, *cpls_base;
+    const int *lanes;            // per sample: 1 (site lanes) or 64 (chain lanes)
     const double *twid;          // per lattice: cos(2 pi n/L), then sin, n < L
     const double *E, *betas;
     const int *beta_base;
@@ -82,10 +121,15 @@ struct MeasParams {
 
 hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_samples,
                              hipStream_t st);
+hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items,
+                                hipStream_t st);
 hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st);
 hipError_t launch_swap(const SwapParams &p, hipStream_t st);
-hipError_t launch_init_spins(float *spins, int64_t spin_base, int L, int C, int T, int sample,
-                             uint32_t key0, uint32_t key1, hipStream_t st);
+hipError_t launch_init_spins(float *spins, int64_t spin_base, int lanes, int L, int C, int T,
+                             int sample, uint32_t key0, uint32_t key1, hipStream_t st);
+int cl_blocks(int L, int split);
+hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, float *canon,
+                           bool to_canon, hipStream_t st);
 hipError_t launch_measure(const MeasParams &p, hipStream_t st);
 
 }  // namespace ptsg

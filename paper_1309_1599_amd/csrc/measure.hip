@@ -20,9 +20,11 @@ constexpr int kS0 = 0, kSxR = 9, kSxI = 18, kSyR = 27, kSyI = 36;       // overl
 constexpr int kK0 = 45, kKxR = 48, kKxI = 51, kKyR = 54, kKyI = 57;     // chiral, 3 each
 constexpr int kSD = 60;                                                  // sd1a sd2a sd1b sd2b
 
+// One chain of a record: generic access to its spins in either layout.
 struct Chain {
-    const float *s;
-    int L, Lh, H;
+    const float *spins;
+    int64_t base;
+    int lanes, j, L, Lh, H;
     __device__ __forceinline__ int packed(int x, int y, int z) const
     {
         return (x >> 1) + Lh * (y + L * z);
@@ -31,10 +33,8 @@ struct Chain {
     {
         const int c = (x + y + z) & 1;
         const int p = packed(x, y, z);
-        const float *o = s + c * 3 * H + p;
-        v[0] = o[0];
-        v[1] = o[H];
-        v[2] = o[2 * H];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = spins[spin_index(base, lanes, H, j, c, k, p)];
     }
 };
 
@@ -79,8 +79,8 @@ __device__ __forceinline__ RecordChains record_chains(const MeasParams &P, int r
     const int ja = ra * T + perm[ra * T + k];
     const int jb = rb * T + perm[rb * T + k];
     RecordChains rc;
-    rc.a = Chain{P.spins + P.spin_base[s] + static_cast<int64_t>(ja) * 6 * H, L, L / 2, H};
-    rc.b = Chain{P.spins + P.spin_base[s] + static_cast<int64_t>(jb) * 6 * H, L, L / 2, H};
+    rc.a = Chain{P.spins, P.spin_base[s], P.lanes[s], ja, L, L / 2, H};
+    rc.b = Chain{P.spins, P.spin_base[s], P.lanes[s], jb, L, L / 2, H};
     rc.s = s;
     rc.L = L;
     rc.cw = P.twid + P.twid_base[s];
@@ -135,29 +135,33 @@ __device__ __forceinline__ double chirality(const Chain &c, int x, int y, int z,
            v[2] * (u[0] * w[1] - u[1] * w[0]);
 }
 
-// FP64 local field from the packed couplings (h = sum_n A_n s_nbr).
-__device__ __forceinline__ void field64(const Chain &c, const float *cpl, int x, int y, int z,
+// FP64 local field from the site-major couplings:
+// h = sum_mu M_{mu,x} s_{x+e_mu} + M_{mu,x-e_mu}^T s_{x-e_mu}.
+__device__ __forceinline__ void field64(const Chain &c, const float *cpls, int x, int y, int z,
                                         double h[3])
 {
-    const int L = c.L, H = c.H;
-    const int col = (x + y + z) & 1;
-    const float *A = cpl + static_cast<int64_t>(col) * 54 * H + c.packed(x, y, z);
+    const int L = c.L;
     const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
     const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
     const int zp = z + 1 == L ? 0 : z + 1, zm = z == 0 ? L - 1 : z - 1;
-    const int nx[6] = {xp, xm, x, x, x, x};
-    const int ny[6] = {y, y, yp, ym, y, y};
-    const int nz[6] = {z, z, z, z, zp, zm};
+    const int pc[3][3] = {{xp, y, z}, {x, yp, z}, {x, y, zp}};
+    const int mc[3][3] = {{xm, y, z}, {x, ym, z}, {x, y, zm}};
+    const int64_t i = x + static_cast<int64_t>(L) * (y + L * z);
     h[0] = h[1] = h[2] = 0.0;
 #pragma unroll
-    for (int n = 0; n < 6; ++n) {
-        double v[3];
-        c.get(nx[n], ny[n], nz[n], v);
+    for (int mu = 0; mu < 3; ++mu) {
+        double vp[3], vm[3];
+        c.get(pc[mu][0], pc[mu][1], pc[mu][2], vp);
+        c.get(mc[mu][0], mc[mu][1], mc[mu][2], vm);
+        const int64_t im = mc[mu][0] + static_cast<int64_t>(L) * (mc[mu][1] + L * mc[mu][2]);
+        const float *F = cpls + i * 27 + mu * 9;
+        const float *B = cpls + im * 27 + mu * 9;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b)
-                h[a] += static_cast<double>(A[static_cast<int64_t>(n * 9 + a * 3 + b) * H]) * v[b];
+                h[a] += static_cast<double>(F[a * 3 + b]) * vp[b] +
+                        static_cast<double>(B[b * 3 + a]) * vm[b];
     }
 }
 
@@ -168,7 +172,7 @@ __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
     const int L = rc.L;
     if (z >= L) return;
     const bool chi = P.what & PT_M_CHIRAL, sd = P.what & PT_M_SD;
-    const float *cpl = P.cpl + P.cpl_base[rc.s];
+    const float *cpl = P.cpls + P.cpls_base[rc.s];
     double acc[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) acc[q] = 0.0;

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -38,26 +39,79 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
-// One lattice class: samples sharing L and the number of temperatures, swept
-// by the same launches.
+// One lattice class: samples sharing L, the number of temperatures and the
+// kernel mapping, swept by the same launches.
 struct LatticeClass {
-    int L = 0, T = 0, C = 0, G = 1, n_site_blocks = 0;
+    int L = 0, T = 0, C = 0, lanes = 1;
+    int G = 1;                       // site lanes: chains per workgroup
+    int split = 1;                   // chain lanes: waves per packed row
+    int blocks = 0;                  // workgroups per (sample or item) and half-sweep
+    int batch = 1;                   // chain lanes: items per launch (Infinity Cache budget)
     std::vector<int> samples;
     int *d_samples = nullptr;
+    std::vector<int> items;          // chain lanes: (sample, group) pairs
+    int *d_items = nullptr;
 };
 
 // Device memory plan of a batch: byte offsets into one workspace.
 struct Plan {
     int S = 0, R = 0, n_chains = 0, Lmax = 0, n_records = 0, e_stride = 1, twid_len = 0;
-    std::vector<int> L, T, chain_base, perm_base, beta_base, twid_base;
-    std::vector<int64_t> spin_base, cpl_base;
-    int64_t spin_floats = 0, cpl_floats = 0;
-    int total_perm = 0;
-    size_t off_spins = 0, off_cpl = 0, off_slot = 0, off_beta_of = 0, off_E = 0, off_perm = 0,
-           off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0, off_mpart = 0,
-           off_meas = 0, off_classes = 0, bytes = 0;
-    size_t meta_ints = 0;
+    std::vector<int> L, T, lanes, chain_base, perm_base, beta_base, twid_base;
+    std::vector<int64_t> spin_base, cpls_base, cpl6_base;
+    int64_t spin_floats = 0, cpls_floats = 0, cpl6_floats = 0;
+    int total_perm = 0, n_items = 0;
+    size_t off_spins = 0, off_cpls = 0, off_cpl6 = 0, off_slot = 0, off_beta_of = 0, off_E = 0,
+           off_perm = 0, off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0,
+           off_mpart = 0, off_meas = 0, off_classes = 0, off_items = 0, off_stage = 0, bytes = 0;
 };
+
+// Chain-lane launches keep the working set of one batch of (sample, group)
+// items -- 64 chains of spins plus the sample's couplings -- inside this
+// share of the 256 MB Infinity Cache.
+constexpr int64_t kCacheBudget = 192ll << 20;
+
+// Largest split of a packed row into wave segments (1, 2, 4 or 8 segments,
+// at least 2 sites each).
+int max_split(int L)
+{
+    const int Lh = L / 2;
+    int best = 1;
+    for (int s = 2; s <= 8; s *= 2)
+        if (Lh % s == 0 && Lh / s >= 2) best = s;
+    return best;
+}
+
+// Items (64-chain groups) per chain-lane launch within the cache budget.
+int cl_batch(int L, int n_items)
+{
+    const int64_t N = static_cast<int64_t>(L) * L * L;
+    const int64_t item = 64 * 3 * N * 4 + 27 * N * 4;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_items, kCacheBudget / item)));
+}
+
+// Segments per packed row.  Whole rows per wave measured fastest at L = 64
+// (the four waves of a workgroup then cover four adjacent rows and share
+// their y-neighbour rows in L1); rows are split only when a launch would
+// otherwise have fewer than 1024 workgroups.
+int choose_split(int L, int batch)
+{
+    const int Lh = L / 2;
+    int best = 1;
+    for (int s = 1; s <= 8; s *= 2) {
+        if (Lh % s || (s > 1 && Lh / s < 2)) continue;
+        best = s;
+        if (static_cast<int64_t>(cl_blocks(L, s)) * batch >= 1024) break;
+    }
+    return best;
+}
+
+int choose_lanes(const pt_batch_desc *d, int s)
+{
+    const int L = d->L[s], C = d->n_replicas * d->n_temps[s];
+    if (d->flags & PT_F_SITE_LANES) return 1;
+    if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? 64 : 1;
+    return (C >= 48 && L <= 128) ? 64 : 1;
+}
 
 std::string validate(const pt_batch_desc *d)
 {
@@ -89,36 +143,47 @@ Plan make_plan(const pt_batch_desc *d)
     p.S = d->n_samples;
     p.R = d->n_replicas;
     int chains = 0, perm = 0, betas = 0, twid = 0;
-    int64_t spins = 0, cpl = 0;
+    int64_t spins = 0, cpls = 0, cpl6 = 0;
     int max_blocks = 1;
     for (int s = 0; s < p.S; ++s) {
         const int L = d->L[s], T = d->n_temps[s];
         const int64_t N = static_cast<int64_t>(L) * L * L;
+        const int C = p.R * T;
+        const int lanes = choose_lanes(d, s);
+        const int C_alloc = (C + lanes - 1) / lanes * lanes;
         p.L.push_back(L);
         p.T.push_back(T);
+        p.lanes.push_back(lanes);
         p.chain_base.push_back(chains);
         p.perm_base.push_back(perm);
         p.beta_base.push_back(betas);
         p.twid_base.push_back(twid);
         p.spin_base.push_back(spins);
-        p.cpl_base.push_back(cpl);
-        chains += p.R * T;
-        perm += p.R * T;
+        p.cpls_base.push_back(cpls);
+        p.cpl6_base.push_back(lanes == 1 ? cpl6 : -1);
+        chains += C;
+        perm += C;
         betas += T;
         twid += 2 * L;
-        spins += static_cast<int64_t>(p.R) * T * 3 * N;
-        cpl += 54 * N;
+        spins += static_cast<int64_t>(C_alloc) * 3 * N;
+        cpls += 27 * N;
+        if (lanes == 1) {
+            cpl6 += 54 * N;
+            max_blocks = std::max<int>(max_blocks, static_cast<int>((N / 2 + kSweepBlock - 1) / kSweepBlock));
+        } else {
+            max_blocks = std::max(max_blocks, cl_blocks(L, max_split(L)));
+            p.n_items += (C + 63) / 64;
+        }
         p.Lmax = std::max(p.Lmax, L);
-        max_blocks = std::max<int>(max_blocks, static_cast<int>((N / 2 + kSweepBlock - 1) / kSweepBlock));
         p.n_records += T * p.R * (p.R - 1) / 2;
     }
     p.n_chains = chains;
     p.total_perm = perm;
     p.spin_floats = spins;
-    p.cpl_floats = cpl;
+    p.cpls_floats = cpls;
+    p.cpl6_floats = cpl6;
     p.e_stride = max_blocks;
     p.twid_len = twid;
-    p.meta_ints = 0;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -126,7 +191,8 @@ Plan make_plan(const pt_batch_desc *d)
         return at;
     };
     p.off_spins = take(sizeof(float) * static_cast<size_t>(spins));
-    p.off_cpl = take(sizeof(float) * static_cast<size_t>(cpl));
+    p.off_cpls = take(sizeof(float) * static_cast<size_t>(cpls));
+    p.off_cpl6 = take(sizeof(float) * static_cast<size_t>(std::max<int64_t>(cpl6, 1)));
     p.off_slot = take(sizeof(int) * chains);
     p.off_beta_of = take(sizeof(float) * chains);
     p.off_E = take(sizeof(double) * chains);
@@ -134,12 +200,15 @@ Plan make_plan(const pt_batch_desc *d)
     p.off_betas = take(sizeof(double) * betas);
     p.off_epart = take(sizeof(double) * static_cast<size_t>(chains) * p.e_stride);
     p.off_twid = take(sizeof(double) * twid);
-    // per-sample int tables: L, n_temps, chain_base, perm_base, beta_base, twid_base
-    p.off_meta = take(sizeof(int) * 6 * p.S + 2 * sizeof(int64_t) * p.S + kAlign);
+    // per-sample tables: spin_base, cpls_base, cpl6_base (int64); L, n_temps,
+    // chain_base, perm_base, beta_base, twid_base, lanes (int)
+    p.off_meta = take(3 * sizeof(int64_t) * p.S + 7 * sizeof(int) * p.S);
     p.off_rec = take(sizeof(int) * 4 * std::max(1, p.n_records));
     p.off_mpart = take(sizeof(double) * static_cast<size_t>(std::max(1, p.n_records)) * p.Lmax * kPlaneQ);
     p.off_meas = take(sizeof(pt_meas) * std::max(1, p.n_records));
     p.off_classes = take(sizeof(int) * p.S);
+    p.off_items = take(sizeof(int) * 2 * std::max(1, p.n_items));
+    p.off_stage = take(sizeof(float) * 3 * static_cast<size_t>(p.Lmax) * p.Lmax * p.Lmax);
     p.bytes = o;
     return p;
 }
@@ -159,13 +228,14 @@ struct pt_ctx {
     char *ws = nullptr;
     bool own_ws = false;
     // device views
-    float *spins = nullptr, *cpl = nullptr, *beta_of = nullptr;
+    float *spins = nullptr, *cpls = nullptr, *cpl6 = nullptr, *beta_of = nullptr;
     int *slot_of = nullptr, *perm = nullptr, *rec = nullptr;
     double *E = nullptr, *betas = nullptr, *epart = nullptr, *twid = nullptr, *mpart = nullptr;
     pt_meas *meas = nullptr;
+    float *stage = nullptr;           // one chain in canonical [N][3] order
     int *d_L = nullptr, *d_T = nullptr, *d_chain_base = nullptr, *d_perm_base = nullptr,
-        *d_beta_base = nullptr, *d_twid_base = nullptr;
-    int64_t *d_spin_base = nullptr, *d_cpl_base = nullptr;
+        *d_beta_base = nullptr, *d_twid_base = nullptr, *d_lanes = nullptr;
+    int64_t *d_spin_base = nullptr, *d_cpls_base = nullptr, *d_cpl6_base = nullptr;
     // profiling
     bool profiling = false;
     std::vector<std::pair<int, Event>> pending;
@@ -176,14 +246,14 @@ struct pt_ctx {
 
 namespace {
 
-SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour)
+SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour, uint32_t hb_sweep)
 {
     SweepParams p{};
     p.spins = c->spins;
-    p.cpl = c->cpl;
+    p.cpl = c->cpl6;
     p.samples = k.d_samples;
     p.spin_base = c->d_spin_base;
-    p.cpl_base = c->d_cpl_base;
+    p.cpl_base = c->d_cpl6_base;
     p.chain_base = c->d_chain_base;
     p.slot_of = c->slot_of;
     p.beta_of = c->beta_of;
@@ -194,8 +264,37 @@ SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour)
     p.C = k.C;
     p.G = k.G;
     p.T = k.T;
+    p.n_tiles = k.blocks;
+    p.per = (k.blocks + 7) / 8;
     p.colour = colour;
-    p.hb_sweep = static_cast<uint32_t>(c->hb_sweeps);
+    p.hb_sweep = hb_sweep;
+    p.key0 = static_cast<uint32_t>(c->seed);
+    p.key1 = static_cast<uint32_t>(c->seed >> 32);
+    return p;
+}
+
+ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour, uint32_t hb_sweep)
+{
+    ClParams p{};
+    p.spins = c->spins;
+    p.cpls = c->cpls;
+    p.items = k.d_items + 2 * first_item;
+    p.spin_base = c->d_spin_base;
+    p.cpls_base = c->d_cpls_base;
+    p.chain_base = c->d_chain_base;
+    p.slot_of = c->slot_of;
+    p.beta_of = c->beta_of;
+    p.e_part = c->epart;
+    p.e_stride = c->plan.e_stride;
+    p.L = k.L;
+    p.H = k.L * k.L * k.L / 2;
+    p.C = k.C;
+    p.T = k.T;
+    p.split = k.split;
+    p.n_tiles = k.blocks;
+    p.per = (k.blocks + 7) / 8;
+    p.colour = colour;
+    p.hb_sweep = hb_sweep;
     p.key0 = static_cast<uint32_t>(c->seed);
     p.key1 = static_cast<uint32_t>(c->seed >> 32);
     return p;
@@ -228,43 +327,94 @@ pt_status drain_events(pt_ctx *c)
     return PT_OK;
 }
 
-// One half-sweep of every class; `energy` fuses the energy partials.
-pt_status half_sweep_all(pt_ctx *c, int kind, int colour, bool energy)
+// Bracket one sweep launch with profiling events when enabled.
+template <class Launch>
+pt_status timed_launch(pt_ctx *c, int kind, Launch launch)
 {
-    for (const auto &k : c->classes) {
-        const SweepParams p = sweep_params(c, k, colour);
-        Event ev;
-        const bool timed = c->profiling && kind != kEnergyOnly;
-        if (timed) {
-            if (c->pending.size() >= 4096) {
-                pt_status st = drain_events(c);
-                if (st != PT_OK) return st;
-            }
-            pt_status st = get_event(c, ev);
+    const bool timed = c->profiling && kind != kEnergyOnly;
+    Event ev;
+    if (timed) {
+        if (c->pending.size() >= 4096) {
+            pt_status st = drain_events(c);
             if (st != PT_OK) return st;
-            PT_HIP(hipEventRecord(ev.a, c->stream));
         }
-        PT_HIP(launch_half_sweep(kind, energy, p, static_cast<int>(k.samples.size()), c->stream));
-        if (timed) {
-            PT_HIP(hipEventRecord(ev.b, c->stream));
-            c->pending.push_back({kind == kOverrelax ? PT_K_OVERRELAX : PT_K_HEATBATH, ev});
-        }
-        if (energy) {
-            EnergyParams e{};
-            e.e_part = c->epart;
-            e.e_stride = c->plan.e_stride;
-            e.n_blocks = k.n_site_blocks;
-            e.samples = k.d_samples;
-            e.chain_base = c->d_chain_base;
-            e.C = k.C;
-            e.E = c->E;
-            PT_HIP(launch_energy_finalize(e, static_cast<int>(k.samples.size()), c->stream));
-        }
+        pt_status st = get_event(c, ev);
+        if (st != PT_OK) return st;
+        PT_HIP(hipEventRecord(ev.a, c->stream));
+    }
+    PT_HIP(launch());
+    if (timed) {
+        PT_HIP(hipEventRecord(ev.b, c->stream));
+        c->pending.push_back({kind == kOverrelax ? PT_K_OVERRELAX : PT_K_HEATBATH, ev});
     }
     return PT_OK;
 }
 
-pt_status refresh_energies(pt_ctx *c) { return half_sweep_all(c, kEnergyOnly, 1, true); }
+pt_status finalize_energies(pt_ctx *c, const LatticeClass &k)
+{
+    EnergyParams e{};
+    e.e_part = c->epart;
+    e.e_stride = c->plan.e_stride;
+    e.n_blocks = k.blocks;
+    e.samples = k.d_samples;
+    e.chain_base = c->d_chain_base;
+    e.C = k.C;
+    e.E = c->E;
+    PT_HIP(launch_energy_finalize(e, static_cast<int>(k.samples.size()), c->stream));
+    return PT_OK;
+}
+
+// The sweeps of one class: `kinds` lists the sweep kinds in order; the
+// heat-bath sweep n of the list uses counter hb0 + n.  The energy partials
+// are fused into the last half-sweep.
+pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &kinds, uint64_t hb0)
+{
+    const int total = static_cast<int>(kinds.size());
+    if (total == 0) return PT_OK;
+    pt_status st;
+    if (k.lanes == 1) {
+        uint64_t hb = hb0;
+        for (int n = 0; n < total; ++n) {
+            const int kind = kinds[n];
+            for (int colour = 0; colour < 2; ++colour) {
+                const bool energy = n == total - 1 && colour == 1;
+                const SweepParams p = sweep_params(c, k, colour, static_cast<uint32_t>(hb));
+                const int ns = static_cast<int>(k.samples.size());
+                st = timed_launch(c, kind, [&] { return launch_half_sweep(kind, energy, p, ns, c->stream); });
+                if (st != PT_OK) return st;
+            }
+            if (kind == kHeatbath) ++hb;
+        }
+    } else {
+        // chain-group-major: every sweep of one batch of items before the next
+        const int n_items = static_cast<int>(k.items.size() / 2);
+        for (int first = 0; first < n_items; first += k.batch) {
+            const int cnt = std::min(k.batch, n_items - first);
+            uint64_t hb = hb0;
+            for (int n = 0; n < total; ++n) {
+                const int kind = kinds[n];
+                for (int colour = 0; colour < 2; ++colour) {
+                    const bool energy = n == total - 1 && colour == 1;
+                    const ClParams p = cl_params(c, k, first, colour, static_cast<uint32_t>(hb));
+                    st = timed_launch(c, kind, [&] { return launch_cl_half_sweep(kind, energy, p, cnt, c->stream); });
+                    if (st != PT_OK) return st;
+                }
+                if (kind == kHeatbath) ++hb;
+            }
+        }
+    }
+    return finalize_energies(c, k);
+}
+
+// Energies of every chain from the current spins (no update).
+pt_status refresh_energies(pt_ctx *c)
+{
+    for (const auto &k : c->classes) {
+        pt_status st = sweep_class(c, k, {kEnergyOnly}, 0);
+        if (st != PT_OK) return st;
+    }
+    return PT_OK;
+}
 
 // Chains per workgroup: enough workgroups to cover the chip several times,
 // as many chains as possible sharing one coupling load.
@@ -362,7 +512,8 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     }
     char *w = c->ws;
     c->spins = reinterpret_cast<float *>(w + P.off_spins);
-    c->cpl = reinterpret_cast<float *>(w + P.off_cpl);
+    c->cpls = reinterpret_cast<float *>(w + P.off_cpls);
+    c->cpl6 = reinterpret_cast<float *>(w + P.off_cpl6);
     c->slot_of = reinterpret_cast<int *>(w + P.off_slot);
     c->beta_of = reinterpret_cast<float *>(w + P.off_beta_of);
     c->E = reinterpret_cast<double *>(w + P.off_E);
@@ -373,32 +524,37 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     c->rec = reinterpret_cast<int *>(w + P.off_rec);
     c->mpart = reinterpret_cast<double *>(w + P.off_mpart);
     c->meas = reinterpret_cast<pt_meas *>(w + P.off_meas);
+    c->stage = reinterpret_cast<float *>(w + P.off_stage);
     {
         char *m = w + P.off_meta;
         c->d_spin_base = reinterpret_cast<int64_t *>(m);
-        c->d_cpl_base = c->d_spin_base + P.S;
-        int *ip = reinterpret_cast<int *>(c->d_cpl_base + P.S);
+        c->d_cpls_base = c->d_spin_base + P.S;
+        c->d_cpl6_base = c->d_spin_base + 2 * P.S;
+        int *ip = reinterpret_cast<int *>(c->d_spin_base + 3 * P.S);
         c->d_L = ip;
         c->d_T = ip + P.S;
         c->d_chain_base = ip + 2 * P.S;
         c->d_perm_base = ip + 3 * P.S;
         c->d_beta_base = ip + 4 * P.S;
         c->d_twid_base = ip + 5 * P.S;
+        c->d_lanes = ip + 6 * P.S;
     }
     hipStream_t st = c->stream;
     // per-sample tables
     {
-        std::vector<char> meta(2 * sizeof(int64_t) * P.S + 6 * sizeof(int) * P.S);
+        std::vector<char> meta(3 * sizeof(int64_t) * P.S + 7 * sizeof(int) * P.S);
         int64_t *lp = reinterpret_cast<int64_t *>(meta.data());
         std::copy(P.spin_base.begin(), P.spin_base.end(), lp);
-        std::copy(P.cpl_base.begin(), P.cpl_base.end(), lp + P.S);
-        int *ip = reinterpret_cast<int *>(lp + 2 * P.S);
+        std::copy(P.cpls_base.begin(), P.cpls_base.end(), lp + P.S);
+        std::copy(P.cpl6_base.begin(), P.cpl6_base.end(), lp + 2 * P.S);
+        int *ip = reinterpret_cast<int *>(lp + 3 * P.S);
         std::copy(P.L.begin(), P.L.end(), ip);
         std::copy(P.T.begin(), P.T.end(), ip + P.S);
         std::copy(P.chain_base.begin(), P.chain_base.end(), ip + 2 * P.S);
         std::copy(P.perm_base.begin(), P.perm_base.end(), ip + 3 * P.S);
         std::copy(P.beta_base.begin(), P.beta_base.end(), ip + 4 * P.S);
         std::copy(P.twid_base.begin(), P.twid_base.end(), ip + 5 * P.S);
+        std::copy(P.lanes.begin(), P.lanes.end(), ip + 6 * P.S);
         PT_HIP(hipMemcpy(w + P.off_meta, meta.data(), meta.size(), hipMemcpyHostToDevice));
     }
     // temperatures, permutation, slots, twiddles, measurement records
@@ -436,42 +592,70 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
         if (!rec.empty())
             PT_HIP(hipMemcpy(c->rec, rec.data(), rec.size() * sizeof(int), hipMemcpyHostToDevice));
     }
-    // couplings: pack on the host, one sample at a time
+    // couplings: site-major copy for every sample, the packed six-matrix
+    // form for site-lane samples
     {
         std::vector<float> buf;
         for (int s = 0; s < P.S; ++s) {
             const int L = P.L[s];
-            buf.assign(static_cast<size_t>(54) * L * L * L, 0.0f);
-            pack_couplings(L, d->couplings[s], buf.data());
-            PT_HIP(hipMemcpy(c->cpl + P.cpl_base[s], buf.data(), buf.size() * sizeof(float),
+            const int64_t N = static_cast<int64_t>(L) * L * L;
+            buf.resize(static_cast<size_t>(27 * N));
+            for (int64_t i = 0; i < N; ++i)
+                for (int mu = 0; mu < 3; ++mu)
+                    std::memcpy(&buf[(i * 3 + mu) * 9], d->couplings[s] + (mu * N + i) * 9, 9 * sizeof(float));
+            PT_HIP(hipMemcpy(c->cpls + P.cpls_base[s], buf.data(), buf.size() * sizeof(float),
                              hipMemcpyHostToDevice));
+            if (P.lanes[s] == 1) {
+                buf.assign(static_cast<size_t>(54 * N), 0.0f);
+                pack_couplings(L, d->couplings[s], buf.data());
+                PT_HIP(hipMemcpy(c->cpl6 + P.cpl6_base[s], buf.data(), buf.size() * sizeof(float),
+                                 hipMemcpyHostToDevice));
+            }
         }
     }
-    // lattice classes (same L and T): one launch per class per half-sweep
+    // lattice classes (same L, T and mapping), swept by the same launches
     {
-        std::map<std::pair<int, int>, std::vector<int>> groups;
-        for (int s = 0; s < P.S; ++s) groups[{P.L[s], P.T[s]}].push_back(s);
+        std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+        for (int s = 0; s < P.S; ++s) groups[{P.L[s], P.T[s], P.lanes[s]}].push_back(s);
         int *dsamp = reinterpret_cast<int *>(w + P.off_classes);
-        int at = 0;
+        int *ditems = reinterpret_cast<int *>(w + P.off_items);
+        int at = 0, at_items = 0;
         for (auto &g : groups) {
             LatticeClass k;
-            k.L = g.first.first;
-            k.T = g.first.second;
+            k.L = std::get<0>(g.first);
+            k.T = std::get<1>(g.first);
+            k.lanes = std::get<2>(g.first);
             k.C = P.R * k.T;
             const int H = k.L * k.L * k.L / 2;
-            k.n_site_blocks = (H + kSweepBlock - 1) / kSweepBlock;
-            k.G = choose_group(H, k.C, static_cast<int>(g.second.size()));
             k.samples = g.second;
             k.d_samples = dsamp + at;
             PT_HIP(hipMemcpy(k.d_samples, g.second.data(), g.second.size() * sizeof(int),
                              hipMemcpyHostToDevice));
             at += static_cast<int>(g.second.size());
+            if (k.lanes == 1) {
+                k.blocks = (H + kSweepBlock - 1) / kSweepBlock;
+                k.G = choose_group(H, k.C, static_cast<int>(g.second.size()));
+            } else {
+                for (int s : g.second)
+                    for (int grp = 0; grp < (k.C + 63) / 64; ++grp) {
+                        k.items.push_back(s);
+                        k.items.push_back(grp);
+                    }
+                const int n_items = static_cast<int>(k.items.size() / 2);
+                k.batch = cl_batch(k.L, n_items);
+                k.split = choose_split(k.L, k.batch);
+                k.blocks = cl_blocks(k.L, k.split);
+                k.d_items = ditems + 2 * at_items;
+                PT_HIP(hipMemcpy(k.d_items, k.items.data(), k.items.size() * sizeof(int),
+                                 hipMemcpyHostToDevice));
+                at_items += n_items;
+            }
             c->classes.push_back(k);
         }
     }
     // hot start, then energies
     for (int s = 0; s < P.S; ++s)
-        PT_HIP(launch_init_spins(c->spins, P.spin_base[s], P.L[s], P.R * P.T[s], P.T[s], s,
+        PT_HIP(launch_init_spins(c->spins, P.spin_base[s], P.lanes[s], P.L[s], P.R * P.T[s], P.T[s], s,
                                  static_cast<uint32_t>(c->seed),
                                  static_cast<uint32_t>(c->seed >> 32), st));
     {
@@ -503,14 +687,11 @@ pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
     if (n_hb < 0 || n_or < 0) return fail(PT_EINVAL, "n_hb and n_or must be >= 0");
-    const int total = n_hb + n_or;
-    for (int n = 0; n < total; ++n) {
-        const int kind = n < n_hb ? kHeatbath : kOverrelax;
-        const bool last = n == total - 1;
-        if ((st = half_sweep_all(c, kind, 0, false)) != PT_OK) return st;
-        if ((st = half_sweep_all(c, kind, 1, last)) != PT_OK) return st;
-        if (kind == kHeatbath) c->hb_sweeps += 1;
-    }
+    std::vector<int> kinds(n_hb, kHeatbath);
+    kinds.insert(kinds.end(), n_or, kOverrelax);
+    for (const auto &k : c->classes)
+        if ((st = sweep_class(c, k, kinds, c->hb_sweeps)) != PT_OK) return st;
+    c->hb_sweeps += n_hb;
     return PT_OK;
 }
 
@@ -554,7 +735,7 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
                                    std::to_string(P.n_records) + " needed");
     MeasParams m{};
     m.spins = c->spins;
-    m.cpl = c->cpl;
+    m.cpls = c->cpls;
     m.rec = c->rec;
     m.perm = c->perm;
     m.perm_base = c->d_perm_base;
@@ -563,7 +744,8 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
     m.chain_base = c->d_chain_base;
     m.twid_base = c->d_twid_base;
     m.spin_base = c->d_spin_base;
-    m.cpl_base = c->d_cpl_base;
+    m.cpls_base = c->d_cpls_base;
+    m.lanes = c->d_lanes;
     m.twid = c->twid;
     m.E = c->E;
     m.betas = c->betas;
@@ -601,18 +783,12 @@ pt_status pt_get_spins(pt_ctx *c, int sample, int rep, int tslot, float *out)
     if (!out) return fail(PT_EINVAL, "output is NULL");
     int j;
     if ((st = chain_of(c, sample, rep, tslot, &j)) != PT_OK) return st;
-    const int L = c->plan.L[sample], N = L * L * L, H = N / 2, Lh = L / 2;
-    std::vector<float> buf(3 * static_cast<size_t>(N));
-    PT_HIP(hipMemcpyAsync(buf.data(), c->spins + c->plan.spin_base[sample] + static_cast<int64_t>(j) * 3 * N,
-                          buf.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    const Plan &P = c->plan;
+    const int L = P.L[sample];
+    const size_t n = 3 * static_cast<size_t>(L) * L * L;
+    PT_HIP(launch_chain_io(c->spins, P.spin_base[sample], P.lanes[sample], L, j, c->stage, true, c->stream));
+    PT_HIP(hipMemcpyAsync(out, c->stage, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
     PT_HIP(hipStreamSynchronize(c->stream));
-    for (int z = 0; z < L; ++z)
-        for (int y = 0; y < L; ++y)
-            for (int x = 0; x < L; ++x) {
-                const int i = x + L * (y + L * z), col = (x + y + z) & 1;
-                const int p = (x >> 1) + Lh * (y + L * z);
-                for (int a = 0; a < 3; ++a) out[3 * i + a] = buf[(col * 3 + a) * static_cast<size_t>(H) + p];
-            }
     return PT_OK;
 }
 
@@ -623,17 +799,11 @@ pt_status pt_set_spins(pt_ctx *c, int sample, int rep, int tslot, const float *i
     if (!in) return fail(PT_EINVAL, "input is NULL");
     int j;
     if ((st = chain_of(c, sample, rep, tslot, &j)) != PT_OK) return st;
-    const int L = c->plan.L[sample], N = L * L * L, H = N / 2, Lh = L / 2;
-    std::vector<float> buf(3 * static_cast<size_t>(N));
-    for (int z = 0; z < L; ++z)
-        for (int y = 0; y < L; ++y)
-            for (int x = 0; x < L; ++x) {
-                const int i = x + L * (y + L * z), col = (x + y + z) & 1;
-                const int p = (x >> 1) + Lh * (y + L * z);
-                for (int a = 0; a < 3; ++a) buf[(col * 3 + a) * static_cast<size_t>(H) + p] = in[3 * i + a];
-            }
-    PT_HIP(hipMemcpyAsync(c->spins + c->plan.spin_base[sample] + static_cast<int64_t>(j) * 3 * N, buf.data(),
-                          buf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    const Plan &P = c->plan;
+    const int L = P.L[sample];
+    const size_t n = 3 * static_cast<size_t>(L) * L * L;
+    PT_HIP(hipMemcpyAsync(c->stage, in, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    PT_HIP(launch_chain_io(c->spins, P.spin_base[sample], P.lanes[sample], L, j, c->stage, false, c->stream));
     if ((st = refresh_energies(c)) != PT_OK) return st;
     PT_HIP(hipStreamSynchronize(c->stream));
     return PT_OK;

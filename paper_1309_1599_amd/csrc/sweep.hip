@@ -11,6 +11,7 @@
 // schedule.
 #include "kernels.hpp"
 #include "philox.hpp"
+#include "spin_update.hpp"
 
 namespace ptsg {
 
@@ -42,100 +43,6 @@ __device__ __forceinline__ Nbr neighbours(int p, int L, int colour)
     n.idx[5] = p + (z == 0 ? (L - 1) * dz : -dz);
     n.site = x + L * row;
     return n;
-}
-
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// Overrelaxation (appendix A.1): reflect about h, keep s.h; renormalise.
-__device__ __forceinline__ void overrelax(float &sx, float &sy, float &sz,
-                                          float hx, float hy, float hz)
-{
-    const float q = hx * hx + hy * hy + hz * hz;
-    if (q > 0.0f) {
-        const float f = 2.0f * (hx * sx + hy * sy + hz * sz) * rcp(q);
-        sx = f * hx - sx;
-        sy = f * hy - sy;
-        sz = f * hz - sz;
-        const float r = rsq(sx * sx + sy * sy + sz * sz);
-        sx *= r; sy *= r; sz *= r;
-    }
-}
-
-// Heat-bath (appendix A.1): draw s from exp(beta s.h) on the sphere.
-// c = cos(theta) about n = h/|h| has density ~ exp(X c), X = beta|h|;
-// inverting the upper tail of its CDF with a uniform v gives
-//   t = 1 - c = -log(1 + v expm1(-2X)) / X    (flat law t = 2v below 2^-60).
-// FP32 evaluation: the argument 1 + v expm1(-2X) equals (1-v) + v e^{-2X},
-// a sum of two positive terms (1-v is exact), which keeps its relative
-// accuracy where it is small; log1p is used where it is not.  The
-// complement p = 1 + c = log1p((1-v) expm1(2X)) / X is evaluated on its own
-// so that sin(theta) = sqrt(t p) stays accurate near both poles.
-// The azimuth 2 pi u2 is measured in the branch-free orthonormal frame of
-// Duff et al. (JCGT 6(1), 2017) around n.
-__device__ __forceinline__ void heatbath(float &sx, float &sy, float &sz,
-                                         float hx, float hy, float hz,
-                                         float beta, float v, float u2)
-{
-    const float hn = sqrtf(hx * hx + hy * hy + hz * hz);
-    const float X = beta * hn;
-    const float u = 1.0f - v;  // exact: v has 24 significant bits at most
-    float nx, ny, nz, t, p;
-    if (X < 0x1p-60f) {
-        nx = 0.0f; ny = 0.0f; nz = 1.0f;
-        t = 2.0f * v;
-        p = 2.0f * u;
-    } else {
-        const float ih = 1.0f / hn;
-        nx = hx * ih; ny = hy * ih; nz = hz * ih;
-        const float w = v * expm1f(-2.0f * X);
-        t = -(w > -0.5f ? log1pf(w) : logf(u + v * expf(-2.0f * X))) / X;
-        p = X <= 40.0f ? log1pf(u * expm1f(2.0f * X)) / X : 2.0f - t;
-    }
-    const float ct = t <= 1.0f ? 1.0f - t : p - 1.0f;
-    const float st = sqrtf(fmaxf(t * p, 0.0f));
-    float sp, cp;
-    sincospif(2.0f * u2, &sp, &cp);
-    const float sg = copysignf(1.0f, nz);
-    const float a = -1.0f / (sg + nz);
-    const float b = nx * ny * a;
-    const float b1x = 1.0f + sg * nx * nx * a, b1y = sg * b, b1z = -sg * nx;
-    const float b2x = b, b2y = sg + ny * ny * a, b2z = -ny;
-    sx = ct * nx + st * (cp * b1x + sp * b2x);
-    sy = ct * ny + st * (cp * b1y + sp * b2y);
-    sz = ct * nz + st * (cp * b1z + sp * b2z);
-    const float r = rsq(sx * sx + sy * sy + sz * sz);
-    sx *= r; sy *= r; sz *= r;
-}
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Buffer-resource access: the chain's base address and size live in
-// SGPRs, each lane supplies a 32-bit byte offset, and the component stride
-// goes in the scalar offset, so addressing costs no vector ALU work.
-// Out-of-range offsets read as zero and drop stores (the size bound).
-using Rsrc = __amdgpu_buffer_rsrc_t;
-constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit dwords (CDNA3/CDNA4)
-
-__device__ __forceinline__ Rsrc make_rsrc(const float *base, unsigned bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(base), 0, static_cast<int>(bytes),
-                                             kRsrcWord3);
-}
-
-__device__ __forceinline__ float ld(Rsrc r, unsigned voff, unsigned soff)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-
-__device__ __forceinline__ void st(Rsrc r, float v, unsigned voff, unsigned soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
 
 // The 21 spin values one lane reads per chain: the three components of
@@ -176,20 +83,8 @@ __device__ __forceinline__ double update(const Gather &g, const float (&A)[54], 
                                          uint32_t site, uint32_t sample, uint32_t ctr3,
                                          uint32_t hb_sweep, uint32_t key0, uint32_t key1, float beta)
 {
-    // 54 chained multiply-adds
     float h[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        h[a] = A[a * 3] * g.n[0][0];
-        h[a] = fmaf(A[a * 3 + 1], g.n[0][1], h[a]);
-        h[a] = fmaf(A[a * 3 + 2], g.n[0][2], h[a]);
-    }
-#pragma unroll
-    for (int n = 1; n < 6; ++n)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) h[a] = fmaf(A[n * 9 + a * 3 + b], g.n[n][b], h[a]);
+    local_field(g.n, [&](int n, int a, int b) { return A[n * 9 + a * 3 + b]; }, h);
     float sx, sy, sz;
     if constexpr (KIND == kHeatbath) {
         const uint4 w = philox10(make_uint4(site, hb_sweep, sample, ctr3), key0, key1);
@@ -212,7 +107,9 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
 {
     constexpr bool kOwn = KIND != kHeatbath;  // heat-bath ignores the old spin
     const int s = P.samples[blockIdx.z];
-    const int p = blockIdx.x * kSweepBlock + threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, P.per);
+    if (tile >= P.n_tiles) return;
+    const int p = tile * kSweepBlock + threadIdx.x;
     const bool active = p < P.H;
     const int pc = active ? p : 0;
     const int c = P.colour;
@@ -282,7 +179,7 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
             double e = 0.0;
 #pragma unroll
             for (int w = 0; w < kSweepBlock / 64; ++w) e += e_wave[w][t];
-            P.e_part[static_cast<int64_t>(cb + j0 + t) * P.e_stride + blockIdx.x] = e;
+            P.e_part[static_cast<int64_t>(cb + j0 + t) * P.e_stride + tile] = e;
         }
     }
 }
@@ -302,8 +199,8 @@ __global__ void energy_finalize_kernel(EnergyParams P)
 
 // Hot start: z = 1 - 2u1 uniform on [-1,1], azimuth 2 pi u2 (uniform law on
 // the sphere), counter (site, 0, sample, tag 2 | start slot j | replica).
-__global__ void init_spins_kernel(float *spins, int L, int H, int T, int sample,
-                                  uint32_t key0, uint32_t key1)
+__global__ void init_spins_kernel(float *spins, int64_t base, int lanes, int L, int H, int T,
+                                  int sample, uint32_t key0, uint32_t key1)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= H) return;
@@ -319,18 +216,43 @@ __global__ void init_spins_kernel(float *spins, int L, int H, int T, int sample,
     float sp, cp;
     sincospif(2.0f * unit23(w.y), &sp, &cp);
     const float r = sqrtf(fmaxf(1.0f - z * z, 0.0f));
-    float *o = spins + static_cast<int64_t>(chain) * 6 * H + colour * 3 * H;
-    o[p] = r * cp;
-    o[H + p] = r * sp;
-    o[2 * H + p] = z;
+    spins[spin_index(base, lanes, H, chain, colour, 0, p)] = r * cp;
+    spins[spin_index(base, lanes, H, chain, colour, 1, p)] = r * sp;
+    spins[spin_index(base, lanes, H, chain, colour, 2, p)] = z;
+}
+
+// Copy one chain between the device layout and canonical [N][3] order.
+__global__ void chain_io_kernel(float *spins, int64_t base, int lanes, int L, int j, float *canon,
+                                int to_canon)
+{
+    const int N = L * L * L;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int x = i % L, y = (i / L) % L, z = i / (L * L);
+    const int c = (x + y + z) & 1;
+    const int p = (x >> 1) + (L >> 1) * (y + L * z);
+    for (int k = 0; k < 3; ++k) {
+        const int64_t q = spin_index(base, lanes, N / 2, j, c, k, p);
+        if (to_canon) canon[3 * i + k] = spins[q];
+        else spins[q] = canon[3 * i + k];
+    }
 }
 
 }  // namespace
 
+hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, float *canon,
+                           bool to_canon, hipStream_t st)
+{
+    const int N = L * L * L;
+    hipLaunchKernelGGL(chain_io_kernel, dim3((N + 255) / 256), dim3(256), 0, st, spins, base, lanes,
+                       L, j, canon, to_canon ? 1 : 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_samples,
                              hipStream_t st)
 {
-    const dim3 grid((p.H + kSweepBlock - 1) / kSweepBlock, (p.C + p.G - 1) / p.G, n_samples);
+    const dim3 grid(kXcds * p.per, (p.C + p.G - 1) / p.G, n_samples);
     const dim3 block(kSweepBlock);
     if (kind == kOverrelax) {
         if (energy) hipLaunchKernelGGL((half_sweep_kernel<kOverrelax, true>), grid, block, 0, st, p);
@@ -351,12 +273,12 @@ hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_init_spins(float *spins, int64_t spin_base, int L, int C, int T, int sample,
-                             uint32_t key0, uint32_t key1, hipStream_t st)
+hipError_t launch_init_spins(float *spins, int64_t spin_base, int lanes, int L, int C, int T,
+                             int sample, uint32_t key0, uint32_t key1, hipStream_t st)
 {
     const int H = L * L * L / 2;
     const dim3 grid((H + 255) / 256, 2, C);
-    hipLaunchKernelGGL(init_spins_kernel, grid, dim3(256), 0, st, spins + spin_base, L, H, T,
+    hipLaunchKernelGGL(init_spins_kernel, grid, dim3(256), 0, st, spins, spin_base, lanes, L, H, T,
                        sample, key0, key1);
     return hipGetLastError();
 }

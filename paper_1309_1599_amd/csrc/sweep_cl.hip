@@ -1,0 +1,225 @@
+// sweep_cl.hip -- checkerboard half-sweeps in the chain-lane mapping.
+//
+// One wave = 64 chains of one sample at the same site: lane l owns chain
+// 64*g + l of chain group g.  All lanes read the same site, so
+//  * the site's bond matrices are wave-uniform: scalar loads bring them
+//    into SGPRs from the site-major couplings [N][3][3][3] (the forward bonds
+//    of a site are one contiguous 108-byte block), costing no vector
+//    registers;
+//  * every spin access is a 256-byte row: the layout of a group is
+//    [colour][H][component][64 lanes], each lane uses the same vector offset
+//    (4*lane), the site enters through the scalar offset and the component
+//    through the instruction's immediate offset (0, 256, 512), so
+//    addressing costs no vector ALU work.
+// Each wave walks a segment of one packed row of the active colour (fixed
+// y, z), so all its offsets advance by one site per step; the loads of the
+// next site are in flight while the current one is updated.
+// One chain group of an L = 64 sample is 201 MB and the sample's couplings
+// 28 MB: together they fit in the 256 MB Infinity Cache, which is why the
+// host runs all sweeps of one group back to back.
+#include "kernels.hpp"
+#include "philox.hpp"
+#include "spin_update.hpp"
+
+namespace ptsg {
+
+namespace {
+
+using CFloat = __attribute__((address_space(4))) const float;
+
+constexpr unsigned kRow = 3u * 64u * 4u;  // bytes of one site of one group: 3 components x 64 lanes
+
+struct ClGather {
+    float o[3];
+    float n[6][3];
+};
+
+__device__ __forceinline__ void load_site(float (&v)[3], Rsrc r, unsigned voff, unsigned soff)
+{
+    v[0] = ld(r, voff + 0u, soff);
+    v[1] = ld(r, voff + 256u, soff);
+    v[2] = ld(r, voff + 512u, soff);
+}
+
+// Byte offsets (scalar) of the 7 sites a lane reads for one update, and the
+// float offsets of the bond matrices in the site-major couplings.
+struct ClSite {
+    unsigned own, nb[6];
+    unsigned fw, bw[3];  // forward block of the site; backward bond mu of site - e_mu
+    int site;            // canonical index
+};
+
+template <bool OWN>
+__device__ __forceinline__ void cl_gather(ClGather &g, Rsrc r, unsigned voff, const ClSite &t)
+{
+#pragma unroll
+    for (int n = 0; n < 6; ++n) load_site(g.n[n], r, voff, t.nb[n]);
+    if constexpr (OWN) load_site(g.o, r, voff, t.own);
+}
+
+template <int KIND, bool ENERGY>
+__global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
+{
+    constexpr bool kOwn = KIND != kHeatbath;
+    const int s = P.items[2 * blockIdx.z];
+    const int g = P.items[2 * blockIdx.z + 1];
+    const int lane = threadIdx.x & 63;
+    // wave-uniform (the compiler cannot infer it from threadIdx.x)
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int j = g * 64 + lane;               // chain of the sample
+    const bool lane_on = j < P.C;
+    const int c = P.colour;
+    const int L = P.L, Lh = L >> 1;
+    const unsigned H = static_cast<unsigned>(P.H);
+    const float *grp = P.spins + P.spin_base[s] + static_cast<int64_t>(g) * 6 * H * 64;
+    const Rsrc r = make_rsrc(grp, 2u * H * kRow);
+    const unsigned voff = 4u * static_cast<unsigned>(lane);
+    // The couplings are read-only for the whole launch: reading them through
+    // the constant address space lets wave-uniform loads become scalar loads.
+    const CFloat *M = (const CFloat *)(P.cpls + P.cpls_base[s]);
+
+    uint32_t ctr3 = 0;
+    float beta = 0.0f;
+    if constexpr (KIND == kHeatbath) {
+        const int chain = P.chain_base[s] + (lane_on ? j : 0);
+        ctr3 = ctr_word3(0u, static_cast<uint32_t>(P.slot_of[chain]), static_cast<uint32_t>(j / P.T));
+        beta = P.beta_of[chain];
+    }
+
+    // This wave's segment: packed row `row` (= y + L*z), x-halves [x0, x0 + len).
+    const int tile = xcd_tile(blockIdx.x, P.per);
+    if (tile >= P.n_tiles) return;
+    const int seg = tile * kClWaves + wave;
+    const int row = seg / P.split;
+    const int len = Lh / P.split;
+    const int x0 = (seg - row * P.split) * len;
+    double e_acc = 0.0;
+    if (row < L * L) {
+        const int y = row % L, z = row / L;
+        const int par = (c + y + z) & 1;              // parity of x along this row
+        const unsigned oth = static_cast<unsigned>(1 - c) * H;
+        const unsigned rowp = static_cast<unsigned>(row * Lh);
+        const unsigned yp = static_cast<unsigned>((y == L - 1 ? row - (L - 1) : row + 1) * Lh);
+        const unsigned ym = static_cast<unsigned>((y == 0 ? row + (L - 1) : row - 1) * Lh);
+        const unsigned zp = static_cast<unsigned>((z == L - 1 ? row - (L - 1) * L : row + L) * Lh);
+        const unsigned zm = static_cast<unsigned>((z == 0 ? row + (L - 1) * L : row - L) * Lh);
+        const int rowc = L * row;                      // canonical index of (0, y, z)
+        const int rym = L * (y == 0 ? row + (L - 1) : row - 1);
+        const int rzm = L * (z == 0 ? row + (L - 1) * L : row - L);
+        // per-row bases; a site adds xh * kRow (spins) or x * 27 (couplings)
+        const unsigned b_own = (static_cast<unsigned>(c) * H + rowp) * kRow;
+        const unsigned b_x = (oth + rowp) * kRow;
+        const unsigned b_yp = (oth + yp) * kRow, b_ym = (oth + ym) * kRow;
+        const unsigned b_zp = (oth + zp) * kRow, b_zm = (oth + zm) * kRow;
+        const unsigned c_fw = static_cast<unsigned>(rowc) * 27u;
+        const unsigned c_by = static_cast<unsigned>(rym) * 27u + 9u;
+        const unsigned c_bz = static_cast<unsigned>(rzm) * 27u + 18u;
+
+        auto site_at = [&](int xh) {
+            ClSite t;
+            const int x = 2 * xh + par;
+            const int xpp = par ? (xh + 1 == Lh ? 0 : xh + 1) : xh;   // packed x of x+1
+            const int xmm = par ? xh : (xh == 0 ? Lh - 1 : xh - 1);   // packed x of x-1
+            const unsigned o = static_cast<unsigned>(xh) * kRow;
+            t.own = b_own + o;
+            t.nb[0] = b_x + static_cast<unsigned>(xpp) * kRow;
+            t.nb[1] = b_x + static_cast<unsigned>(xmm) * kRow;
+            t.nb[2] = b_yp + o;
+            t.nb[3] = b_ym + o;
+            t.nb[4] = b_zp + o;
+            t.nb[5] = b_zm + o;
+            t.site = rowc + x;
+            const unsigned x27 = static_cast<unsigned>(x) * 27u;
+            t.fw = c_fw + x27;
+            t.bw[0] = c_fw + (x == 0 ? static_cast<unsigned>(L - 1) * 27u : x27 - 27u);
+            t.bw[1] = c_by + x27;
+            t.bw[2] = c_bz + x27;
+            return t;
+        };
+
+        auto process = [&](const ClGather &gt, const ClSite &t) {
+            // A_{2mu} = M_{mu,x} (forward), A_{2mu+1} = M_{mu,x-e_mu}^T (backward)
+            const CFloat *F = M + t.fw;
+            const CFloat *B0 = M + t.bw[0], *B1 = M + t.bw[1], *B2 = M + t.bw[2];
+            float h[3];
+            local_field(gt.n, [&](int n, int a, int b) {
+                const int mu = n >> 1;
+                const CFloat *Bm = mu == 0 ? B0 : (mu == 1 ? B1 : B2);
+                return (n & 1) ? Bm[b * 3 + a] : F[mu * 9 + a * 3 + b];
+            }, h);
+            float sx, sy, sz;
+            if constexpr (KIND == kHeatbath) {
+                const uint4 w = philox10(make_uint4(static_cast<uint32_t>(t.site), P.hb_sweep,
+                                                    static_cast<uint32_t>(s), ctr3),
+                                         P.key0, P.key1);
+                heatbath(sx, sy, sz, h[0], h[1], h[2], beta, unit23(w.x), unit23(w.y));
+            } else {
+                sx = gt.o[0]; sy = gt.o[1]; sz = gt.o[2];
+                if constexpr (KIND == kOverrelax) overrelax(sx, sy, sz, h[0], h[1], h[2]);
+            }
+            if (KIND != kEnergyOnly && lane_on) {
+                st(r, sx, voff + 0u, t.own);
+                st(r, sy, voff + 256u, t.own);
+                st(r, sz, voff + 512u, t.own);
+            }
+            if constexpr (ENERGY)
+                e_acc += static_cast<double>(sx) * h[0] + static_cast<double>(sy) * h[1] +
+                         static_cast<double>(sz) * h[2];
+        };
+
+        // software pipeline: the loads of the next site are issued before
+        // the current site is updated
+        ClGather ga, gb;
+        ClSite ta = site_at(x0), tb;
+        cl_gather<kOwn>(ga, r, voff, ta);
+        for (int xh = x0; xh < x0 + len; xh += 2) {
+            const bool has_b = xh + 1 < x0 + len;
+            if (has_b) {
+                tb = site_at(xh + 1);
+                cl_gather<kOwn>(gb, r, voff, tb);
+            }
+            process(ga, ta);
+            if (!has_b) break;
+            if (xh + 2 < x0 + len) {
+                ta = site_at(xh + 2);
+                cl_gather<kOwn>(ga, r, voff, ta);
+            }
+            process(gb, tb);
+        }
+    }
+
+    if constexpr (ENERGY) {
+        // the four waves hold the same 64 chains: reduce them in a fixed order
+        __shared__ double e_wave[kClWaves][64];
+        e_wave[wave][lane] = e_acc;
+        __syncthreads();
+        if (wave == 0 && lane_on) {
+            double e = 0.0;
+#pragma unroll
+            for (int w = 0; w < kClWaves; ++w) e += e_wave[w][lane];
+            P.e_part[static_cast<int64_t>(P.chain_base[s] + j) * P.e_stride + tile] = e;
+        }
+    }
+}
+
+}  // namespace
+
+int cl_blocks(int L, int split) { return (L * L * split + kClWaves - 1) / kClWaves; }
+
+hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items, hipStream_t st)
+{
+    const dim3 grid(kXcds * p.per, 1, n_items);
+    const dim3 block(kClBlock);
+    if (kind == kOverrelax) {
+        if (energy) hipLaunchKernelGGL((cl_half_sweep_kernel<kOverrelax, true>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((cl_half_sweep_kernel<kOverrelax, false>), grid, block, 0, st, p);
+    } else if (kind == kHeatbath) {
+        if (energy) hipLaunchKernelGGL((cl_half_sweep_kernel<kHeatbath, true>), grid, block, 0, st, p);
+        else hipLaunchKernelGGL((cl_half_sweep_kernel<kHeatbath, false>), grid, block, 0, st, p);
+    } else {
+        hipLaunchKernelGGL((cl_half_sweep_kernel<kEnergyOnly, true>), grid, block, 0, st, p);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ptsg

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libptsg.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PT_M_OVERLAP, PT_M_CHIRAL, PT_M_SD, PT_M_ALL = 1, 2, 4, 7
 PT_K_OVERRELAX, PT_K_HEATBATH = 0, 1
+PT_F_SITE_LANES, PT_F_CHAIN_LANES = 1, 2
 
 # numpy view of the C struct pt_meas (744 bytes, no padding)
 MEAS_DTYPE = np.dtype([
@@ -50,7 +51,8 @@ class pt_batch_desc(C.Structure):
                 ("seed", C.c_uint64),
                 ("stream", C.c_void_p),
                 ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t)]
+                ("workspace_bytes", C.c_size_t),
+                ("flags", C.c_uint)]
 
 
 _lib = None
@@ -138,7 +140,7 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def _desc(L, couplings, temps, n_replicas, seed, stream=None, workspace=None, nbytes=0):
+def _desc(L, couplings, temps, n_replicas, seed, stream=None, workspace=None, nbytes=0, flags=0):
     S = len(L)
     keep = [_f32(c).reshape(-1) for c in couplings], [_f64(t) for t in temps]
     Ls = (C.c_int * S)(*[int(x) for x in L])
@@ -146,32 +148,33 @@ def _desc(L, couplings, temps, n_replicas, seed, stream=None, workspace=None, nb
     tp = (C.POINTER(C.c_double) * S)(*[t.ctypes.data_as(C.POINTER(C.c_double)) for t in keep[1]])
     cp = (C.POINTER(C.c_float) * S)(*[c.ctypes.data_as(C.POINTER(C.c_float)) for c in keep[0]])
     d = pt_batch_desc(S, Ls, Ts, tp, cp, int(n_replicas), int(seed) & (2 ** 64 - 1),
-                      stream, workspace, nbytes)
+                      stream, workspace, nbytes, int(flags))
     return d, (keep, Ls, Ts, tp, cp)
 
 
-def pt_workspace_size(L, couplings, temps, n_replicas, seed=0):
-    d, _keep = _desc(L, couplings, temps, n_replicas, seed)
+def pt_workspace_size(L, couplings, temps, n_replicas, seed=0, flags=0):
+    d, _keep = _desc(L, couplings, temps, n_replicas, seed, flags=flags)
     return load_library().pt_workspace_size(C.byref(d))
 
 
-def pt_init_batch(L, couplings, temps, n_replicas, seed, stream=None, device=None):
+def pt_init_batch(L, couplings, temps, n_replicas, seed, stream=None, device=None, flags=0):
     """Batch of samples: L[s], couplings[s] ([3][L^3][3][3] float32), temps[s].
     The workspace is a torch uint8 tensor on `device` (default: current);
-    work goes to `stream` (default: torch's current stream)."""
+    work goes to `stream` (default: torch's current stream); `flags` are the
+    PT_F_* mapping choices (0 = automatic)."""
     import torch
     lib = load_library()
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     with torch.cuda.device(dev):
-        nbytes = pt_workspace_size(L, couplings, temps, n_replicas, seed)
+        nbytes = pt_workspace_size(L, couplings, temps, n_replicas, seed, flags)
         if nbytes == 0:
-            d, _k = _desc(L, couplings, temps, n_replicas, seed)
+            d, _k = _desc(L, couplings, temps, n_replicas, seed, flags=flags)
             h = C.c_void_p()
             _check(lib.pt_init_batch(C.byref(h), C.byref(d)))  # raises with the reason
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         st = (stream if stream is not None else torch.cuda.current_stream(dev)).cuda_stream
         d, _keep = _desc(L, couplings, temps, n_replicas, seed, C.c_void_p(st),
-                         C.c_void_p(ws.data_ptr()), nbytes)
+                         C.c_void_p(ws.data_ptr()), nbytes, flags)
         h = C.c_void_p()
         _check(lib.pt_init_batch(C.byref(h), C.byref(d)))
     return PtContext(h.value, L, [len(t) for t in temps], n_replicas, ws)

@@ -23,10 +23,13 @@ def _gpu():
     ptsg.load_library()
 
 
-def _ctx(Ls, temps, R, seed, cpl=None):
+MAPPINGS = {"site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES}
+
+
+def _ctx(Ls, temps, R, seed, cpl=None, flags=0):
     if cpl is None:
         cpl = [inputs.gaussian_couplings(L, seed, s) for s, L in enumerate(Ls)]
-    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed)
+    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
     return ctx, cpl
 
 
@@ -41,9 +44,10 @@ def _set_random_states(ctx, seed):
     return states
 
 
-def test_init_matches_oracle():
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_init_matches_oracle(mapping):
     L, T, R, seed = 8, 4, 2, 17
-    ctx, cpl = _ctx([L], [inputs.linear_temps(0.5, 2.0, T)], R, seed)
+    ctx, cpl = _ctx([L], [inputs.linear_temps(0.5, 2.0, T)], R, seed, flags=MAPPINGS[mapping])
     E = ptsg.pt_get_energy(ctx)[0]
     M = cpl[0].astype(np.float64)
     for r in range(R):
@@ -54,11 +58,12 @@ def test_init_matches_oracle():
             assert_energy_close(E[r, k], L, M, g, what="init")
 
 
+@pytest.mark.parametrize("mapping", MAPPINGS)
 @pytest.mark.parametrize("L", [4, 8, 12, 16])
-def test_overrelaxation_sweep_parity(L):
+def test_overrelaxation_sweep_parity(L, mapping):
     T, R, seed = 3, 2, 100 + L
     temps = inputs.geometric_temps(0.6, 1.6, T)
-    ctx, cpl = _ctx([L], [temps], R, seed)
+    ctx, cpl = _ctx([L], [temps], R, seed, flags=MAPPINGS[mapping])
     states = _set_random_states(ctx, seed)
     ptsg.pt_step(ctx, 0, 1)
     E = ptsg.pt_get_energy(ctx)[0]
@@ -72,11 +77,12 @@ def test_overrelaxation_sweep_parity(L):
         assert abs(E[r, k] - O.energy(L, M, st)) <= 1e-6 * energy_scale(L, M, st)
 
 
+@pytest.mark.parametrize("mapping", MAPPINGS)
 @pytest.mark.parametrize("L", [8, 12])
-def test_heatbath_sweep_parity(L):
+def test_heatbath_sweep_parity(L, mapping):
     T, R, seed = 4, 2, 200 + L
     temps = inputs.geometric_temps(0.5, 2.0, T)
-    ctx, cpl = _ctx([L], [temps], R, seed)
+    ctx, cpl = _ctx([L], [temps], R, seed, flags=MAPPINGS[mapping])
     states = _set_random_states(ctx, seed)
     ptsg.pt_step(ctx, 1, 0)
     assert ptsg.pt_get_counters(ctx) == (1, 0)
@@ -95,13 +101,14 @@ def test_heatbath_sweep_parity(L):
         assert_spins_close(ptsg.pt_get_spins(ctx, s, r, k), ref, hmag, "HB second sweep")
 
 
-def test_uneven_batch_parity():
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_uneven_batch_parity(mapping):
     """Samples of different L and T in one context, swept together."""
     Ls = [8, 12, 8, 6]
     Ts = [2, 3, 2, 1]
     R, seed = 2, 300
     temps = [inputs.geometric_temps(0.7, 1.5, T) for T in Ts]
-    ctx, cpl = _ctx(Ls, temps, R, seed)
+    ctx, cpl = _ctx(Ls, temps, R, seed, flags=MAPPINGS[mapping])
     states = _set_random_states(ctx, seed)
     ptsg.pt_step(ctx, 1, 1)
     E = ptsg.pt_get_energy(ctx)
@@ -120,10 +127,11 @@ def test_uneven_batch_parity():
         assert_energy_close(E[s][r, k], L, M, ref, rel=1e-5, what="uneven batch")
 
 
-def test_tempering_bit_exact():
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_tempering_bit_exact(mapping):
     L, T, R, seed = 8, 8, 2, 400
     temps = inputs.linear_temps(0.5, 2.0, T)
-    ctx, cpl = _ctx([L], [temps], R, seed)
+    ctx, cpl = _ctx([L], [temps], R, seed, flags=MAPPINGS[mapping])
     beta = 1.0 / temps
     for p in range(6):
         ptsg.pt_step(ctx, 1, 2)
@@ -139,13 +147,14 @@ def test_tempering_bit_exact():
     assert ptsg.pt_get_counters(ctx)[1] == 6
 
 
-def test_heatbath_uses_current_slot():
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_heatbath_uses_current_slot(mapping):
     """After swaps, a chain's heat-bath draws follow its new slot's counter
     and temperature."""
     L, T, R, seed = 8, 4, 2, 450
     # nearly equal temperatures: most proposals are accepted
     temps = inputs.linear_temps(1.0, 1.003, T)
-    ctx, cpl = _ctx([L], [temps], R, seed)
+    ctx, cpl = _ctx([L], [temps], R, seed, flags=MAPPINGS[mapping])
     M = cpl[0].astype(np.float64)
     for _ in range(4):
         ptsg.pt_step(ctx, 1, 1)
@@ -169,11 +178,12 @@ def _oracle_record(L, M, sa, sb):
     return rec
 
 
+@pytest.mark.parametrize("mapping", MAPPINGS)
 @pytest.mark.parametrize("Ls,R", [([8], 2), ([6, 10], 3)])
-def test_measure_parity(Ls, R):
+def test_measure_parity(Ls, R, mapping):
     seed = 500
     temps = [inputs.geometric_temps(0.6, 1.6, 3) for _ in Ls]
-    ctx, cpl = _ctx(Ls, temps, R, seed)
+    ctx, cpl = _ctx(Ls, temps, R, seed, flags=MAPPINGS[mapping])
     for _ in range(3):
         ptsg.pt_step(ctx, 1, 2)
         ptsg.pt_swap(ctx)
@@ -217,6 +227,33 @@ def test_overrelaxation_conserves_energy_many_sweeps():
         for k in range(T):
             s = ptsg.pt_get_spins(ctx, 0, r, k)
             assert np.abs(np.linalg.norm(s, axis=1) - 1).max() < 1e-6
+
+
+def test_mappings_bit_identical():
+    """Both kernel mappings apply the same arithmetic in the same order: the
+    spins after heat-bath and overrelaxation sweeps and tempering passes are
+    bit-identical, on a sample with more chains than one wave (ragged last
+    group) and a lattice whose rows do not split evenly."""
+    Ls = [12, 8]
+    T, R, seed = 35, 2, 650  # 70 chains: groups of 64 + 6
+    temps = [inputs.geometric_temps(0.6, 1.6, T)] * 2
+    out = {}
+    for name, flag in MAPPINGS.items():
+        ctx, _ = _ctx(Ls, temps, R, seed, flags=flag)
+        for _ in range(2):
+            ptsg.pt_step(ctx, 1, 2)
+            ptsg.pt_swap(ctx)
+        out[name] = ([ptsg.pt_get_spins(ctx, s, r, k) for s in range(2) for r in range(R)
+                      for k in (0, 17, 34)],
+                     [ptsg.pt_get_perm(ctx, s, r) for s in range(2) for r in range(R)],
+                     ptsg.pt_get_energy(ctx))
+        ptsg.pt_free(ctx)
+    for a, b in zip(out["site"][0], out["chain"][0]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(out["site"][1], out["chain"][1]):
+        np.testing.assert_array_equal(a, b)
+    for a, b in zip(out["site"][2], out["chain"][2]):
+        np.testing.assert_allclose(a, b, rtol=1e-12)
 
 
 def test_deterministic_replay():
