@@ -24,8 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz
+FLOPS_PER_SU = 138
 METRIC = "ps per spin update (all chains) & HBM roofline %, batched FP32 vs plain FP64"
 KERNEL_SOURCES = ["paper_1309_1599_amd/csrc/sweep.hip", "paper_1309_1599_amd/csrc/sweep_cl.hip",
+                  "paper_1309_1599_amd/csrc/sweep_rs.hip",
                   "paper_1309_1599_amd/csrc/spin_update.hpp", "paper_1309_1599_amd/csrc/kernels.hpp",
                   "paper_1309_1599_amd/csrc/philox.hpp"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "overrelax_half_sweep_L64x8_pmc.txt")
@@ -89,8 +92,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--preset", default="L64x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mapping", choices=("auto", "site", "chain"), default="auto",
-                    help="sweep kernel mapping (auto: chain lanes when a sample has >= 48 chains)")
+    ap.add_argument("--mapping", choices=("auto", "site", "chain", "resident"), default="auto",
+                    help="sweep kernel mapping (auto: resident for L <= 16, else chain lanes when "
+                         "a sample's chains fill 64-lane waves to >= 90%%)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path does not "
@@ -117,9 +121,16 @@ def main():
     b.copy_(a)
     del a, b
 
-    flags = {"auto": 0, "site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES}[args.mapping]
+    flags = {"auto": 0, "site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES,
+             "resident": ptsg.PT_F_RESIDENT}[args.mapping]
     C_sample = R * len(temps[0])
-    mapping = args.mapping if args.mapping != "auto" else ("chain" if C_sample >= 48 and L <= 128 else "site")
+    if args.mapping != "auto":
+        mapping = args.mapping
+    elif L <= 16:
+        mapping = "resident"
+    else:
+        waves = (C_sample + 63) // 64
+        mapping = "chain" if L <= 128 and 10 * C_sample >= 9 * 64 * waves else "site"
     ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
     n_chains = ctx.n_chains
     N = L ** 3
@@ -145,17 +156,39 @@ def main():
     wall = time.perf_counter() - t0
     n_or_launch, or_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_OVERRELAX)
     n_hb_launch, hb_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_HEATBATH)
+    n_rs_launch, rs_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_RESIDENT)
     ptsg.pt_profile(ctx, False)
 
     ps_per_su = wall / (args.steps * su_per_step) * 1e12
     C = R * len(temps[0])
-    bytes_per_su = 24.0 + 108.0 / C           # spin read + write, couplings shared by C chains
-    # overrelaxation spin updates in the timed region, over all launches
-    or_su = args.steps * n_or * n_chains * N
-    su_per_launch = or_su / max(1, n_or_launch)
-    avg_or_s = or_ms / max(1, n_or_launch) / 1e3
-    achieved = bytes_per_su * su_per_launch / avg_or_s / 1e9
-    traffic = pmc_traffic(kernel_hash())
+    if mapping != "resident":
+        # HBM roofline of the overrelaxation half-sweep: per spin update the
+        # method must read and write the spin (24 B) and read the couplings
+        # of the site (108 B), which the C chains of a sample share
+        bytes_per_su = 24.0 + 108.0 / C
+        or_su = args.steps * n_or * n_chains * N       # over all launches of the timed region
+        su_per_launch = or_su / max(1, n_or_launch)
+        avg_s = or_ms / max(1, n_or_launch) / 1e3
+        achieved = bytes_per_su * su_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": ("cl_half_sweep_kernel<overrelax>" if mapping == "chain"
+                                           else "half_sweep_kernel<overrelax>"),
+                "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": pmc_traffic(kernel_hash()),
+                "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
+                "bytes_per_su": round(bytes_per_su, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
+                "launches": n_or_launch}
+    else:
+        # the lattice stays in LDS for the whole step: bounded by FP32 vector
+        # arithmetic, 138 flops per overrelaxation update (54-term field,
+        # reflection, renormalisation); packed FP32 is not used
+        su_per_launch = su_per_step * args.steps / max(1, n_rs_launch)
+        avg_s = rs_ms / max(1, n_rs_launch) / 1e3
+        achieved = FLOPS_PER_SU * su_per_launch / avg_s / 1e12
+        roof = {"bound": "alu", "kernel": "resident_step_kernel", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None, "flops_per_su": FLOPS_PER_SU, "avg_launch_ms": round(avg_s * 1e3, 4),
+                "launches": n_rs_launch}
+    roof["kernel_source_sha256"] = kernel_hash()
 
     result = {
         "metric": METRIC,
@@ -178,21 +211,7 @@ def main():
             "spin_updates_per_step": su_per_step,
             "mapping": mapping + " lanes",
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": ("cl_half_sweep_kernel<overrelax>" if mapping == "chain"
-                       else "half_sweep_kernel<overrelax>"),
-            "achieved": round(achieved, 1),
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
-            "bytes_per_su": round(bytes_per_su, 4),
-            "avg_launch_ms": round(avg_or_s * 1e3, 4),
-            "launches": n_or_launch,
-            "kernel_source_sha256": kernel_hash(),
-        },
+        "roofline": roof,
         "heatbath_avg_launch_ms": round(hb_ms / max(1, n_hb_launch), 4),
     }
     if not args.no_cpu_baseline:

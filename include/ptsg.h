@@ -112,16 +112,22 @@ typedef struct {
     unsigned flags;                /* PT_F_* below; 0 = automatic choices */
 } pt_batch_desc;
 
-/* Kernel mapping of the sweeps (results are bit-identical in both):
+/* Kernel mapping of the sweeps (the spins are bit-identical in all three):
  * site lanes: one lane per site, a workgroup loops over the chains of a
  *   sample with the site's couplings held in registers;
  * chain lanes: one wave = 64 chains of a sample at one site, couplings in
  *   scalar registers; each 64-chain group runs all sweeps of a step back to
- *   back so that its working set stays in the 256 MB Infinity Cache.
- * Automatic: chain lanes when a sample has >= 48 chains and L <= 128. */
+ *   back so that its working set stays in the 256 MB Infinity Cache;
+ * resident: one workgroup per chain keeps the whole lattice in LDS for all
+ *   sweeps of a step (L <= 16).
+ * Automatic: resident for L <= 16, else chain lanes when L <= 128 and the
+ * sample's chains fill its 64-lane waves to >= 90%, else site lanes.  A forced mapping that does not
+ * apply to a sample (resident with L > 16, chain lanes with L > 128) falls
+ * back to site lanes for it. */
 enum {
     PT_F_SITE_LANES = 1u,
-    PT_F_CHAIN_LANES = 2u
+    PT_F_CHAIN_LANES = 2u,
+    PT_F_RESIDENT = 4u
 };
 
 /* One sample (the single-lattice form of the API).  Equivalent to
@@ -183,7 +189,7 @@ pt_status pt_sync(pt_ctx *ctx);
  * HIP events on the context's stream; pt_kernel_time synchronises and
  * returns, for one kernel kind, the number of launches and their summed
  * device time since profiling was (re-)enabled. */
-enum { PT_K_OVERRELAX = 0, PT_K_HEATBATH = 1 };
+enum { PT_K_OVERRELAX = 0, PT_K_HEATBATH = 1, PT_K_RESIDENT = 2 /* whole-step launches */ };
 pt_status pt_profile(pt_ctx *ctx, int enable);
 pt_status pt_kernel_time(pt_ctx *ctx, int kind, uint64_t *launches, double *ms);
 

@@ -32,6 +32,8 @@ constexpr int kMeasBlock = 256;
 constexpr int kClWaves = 4;        // chain-lane mapping: waves per workgroup
 constexpr int kClBlock = 64 * kClWaves;
 constexpr int kClSites = 16;       // consecutive packed sites per wave
+constexpr int kRsMaxBlock = 1024;  // lattice-resident mapping: threads per workgroup (max)
+constexpr int kRsMaxL = 16;        // largest L whose chain (12 N bytes) is kept in LDS
 constexpr int kOverlapQ = 45;      // plane partials: Q(0), Q(kx), Q(ky) re/im, 9 each
 constexpr int kChiralQ = 19;       // kappa(0), kappa(kx), kappa(ky) re/im, 3 each; 4 SD sums
 constexpr int kPlaneQ = kOverlapQ + kChiralQ;
@@ -84,6 +86,20 @@ struct ClParams {
     uint32_t hb_sweep, key0, key1;
 };
 
+// Lattice-resident mapping: one workgroup per chain, spins in LDS for a step.
+struct RsParams {
+    float *spins;
+    const float *cpl;            // packed six-matrix couplings (site-lane layout)
+    const int *samples;
+    const int64_t *spin_base, *cpl_base;
+    const int *chain_base, *slot_of;
+    const float *beta_of;
+    double *E;
+    int L, H, C, T;
+    int n_hb, n_or, energy_only;
+    uint32_t hb_sweep, key0, key1;
+};
+
 struct SwapParams {
     int *perm;                   // [sample][rep][T]: chain j at each slot
     int *slot_of;
@@ -123,6 +139,8 @@ hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_
                              hipStream_t st);
 hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items,
                                 hipStream_t st);
+hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st);
+int rs_block(int L);
 hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st);
 hipError_t launch_swap(const SwapParams &p, hipStream_t st);
 hipError_t launch_init_spins(float *spins, int64_t spin_base, int lanes, int L, int C, int T,

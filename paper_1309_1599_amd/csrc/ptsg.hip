@@ -41,8 +41,10 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // One lattice class: samples sharing L, the number of temperatures and the
 // kernel mapping, swept by the same launches.
+enum Mapping { kSiteLanes = 0, kChainLanes = 1, kResident = 2 };
+
 struct LatticeClass {
-    int L = 0, T = 0, C = 0, lanes = 1;
+    int L = 0, T = 0, C = 0, lanes = 1, mapping = kSiteLanes;
     int G = 1;                       // site lanes: chains per workgroup
     int split = 1;                   // chain lanes: waves per packed row
     int blocks = 0;                  // workgroups per (sample or item) and half-sweep
@@ -56,7 +58,7 @@ struct LatticeClass {
 // Device memory plan of a batch: byte offsets into one workspace.
 struct Plan {
     int S = 0, R = 0, n_chains = 0, Lmax = 0, n_records = 0, e_stride = 1, twid_len = 0;
-    std::vector<int> L, T, lanes, chain_base, perm_base, beta_base, twid_base;
+    std::vector<int> L, T, lanes, mapping, chain_base, perm_base, beta_base, twid_base;
     std::vector<int64_t> spin_base, cpls_base, cpl6_base;
     int64_t spin_floats = 0, cpls_floats = 0, cpl6_floats = 0;
     int total_perm = 0, n_items = 0;
@@ -105,12 +107,16 @@ int choose_split(int L, int batch)
     return best;
 }
 
-int choose_lanes(const pt_batch_desc *d, int s)
+int choose_mapping(const pt_batch_desc *d, int s)
 {
     const int L = d->L[s], C = d->n_replicas * d->n_temps[s];
-    if (d->flags & PT_F_SITE_LANES) return 1;
-    if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? 64 : 1;
-    return (C >= 48 && L <= 128) ? 64 : 1;
+    if (d->flags & PT_F_SITE_LANES) return kSiteLanes;
+    if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
+    if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
+    if (L <= kRsMaxL) return kResident;
+    // chain lanes only when the 64-lane waves are (nearly) full
+    const int waves = (C + 63) / 64;
+    return (L <= 128 && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
 }
 
 std::string validate(const pt_batch_desc *d)
@@ -149,18 +155,20 @@ Plan make_plan(const pt_batch_desc *d)
         const int L = d->L[s], T = d->n_temps[s];
         const int64_t N = static_cast<int64_t>(L) * L * L;
         const int C = p.R * T;
-        const int lanes = choose_lanes(d, s);
+        const int mapping = choose_mapping(d, s);
+        const int lanes = mapping == kChainLanes ? 64 : 1;
         const int C_alloc = (C + lanes - 1) / lanes * lanes;
         p.L.push_back(L);
         p.T.push_back(T);
         p.lanes.push_back(lanes);
+        p.mapping.push_back(mapping);
         p.chain_base.push_back(chains);
         p.perm_base.push_back(perm);
         p.beta_base.push_back(betas);
         p.twid_base.push_back(twid);
         p.spin_base.push_back(spins);
         p.cpls_base.push_back(cpls);
-        p.cpl6_base.push_back(lanes == 1 ? cpl6 : -1);
+        p.cpl6_base.push_back(lanes == 1 ? cpl6 : -1);  // site-lane and resident mappings
         chains += C;
         perm += C;
         betas += T;
@@ -240,8 +248,8 @@ struct pt_ctx {
     bool profiling = false;
     std::vector<std::pair<int, Event>> pending;
     std::vector<Event> free_events;
-    uint64_t prof_launches[2] = {0, 0};
-    double prof_ms[2] = {0.0, 0.0};
+    uint64_t prof_launches[3] = {0, 0, 0};
+    double prof_ms[3] = {0.0, 0.0, 0.0};
 };
 
 namespace {
@@ -327,6 +335,8 @@ pt_status drain_events(pt_ctx *c)
     return PT_OK;
 }
 
+constexpr int kResidentKind = 3;  // profiling tag of whole-step resident launches
+
 // Bracket one sweep launch with profiling events when enabled.
 template <class Launch>
 pt_status timed_launch(pt_ctx *c, int kind, Launch launch)
@@ -345,7 +355,8 @@ pt_status timed_launch(pt_ctx *c, int kind, Launch launch)
     PT_HIP(launch());
     if (timed) {
         PT_HIP(hipEventRecord(ev.b, c->stream));
-        c->pending.push_back({kind == kOverrelax ? PT_K_OVERRELAX : PT_K_HEATBATH, ev});
+        c->pending.push_back({kind == kOverrelax ? PT_K_OVERRELAX
+                              : kind == kHeatbath ? PT_K_HEATBATH : PT_K_RESIDENT, ev});
     }
     return PT_OK;
 }
@@ -372,6 +383,32 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
     const int total = static_cast<int>(kinds.size());
     if (total == 0) return PT_OK;
     pt_status st;
+    if (k.mapping == kResident) {
+        // one launch for the whole list: heat-bath sweeps first, then overrelaxation
+        RsParams p{};
+        p.spins = c->spins;
+        p.cpl = c->cpl6;
+        p.samples = k.d_samples;
+        p.spin_base = c->d_spin_base;
+        p.cpl_base = c->d_cpl6_base;
+        p.chain_base = c->d_chain_base;
+        p.slot_of = c->slot_of;
+        p.beta_of = c->beta_of;
+        p.E = c->E;
+        p.L = k.L;
+        p.H = k.L * k.L * k.L / 2;
+        p.C = k.C;
+        p.T = k.T;
+        p.energy_only = kinds[0] == kEnergyOnly;
+        p.n_hb = p.energy_only ? 0 : static_cast<int>(std::count(kinds.begin(), kinds.end(), kHeatbath));
+        p.n_or = p.energy_only ? 1 : total - p.n_hb;
+        p.hb_sweep = static_cast<uint32_t>(hb0);
+        p.key0 = static_cast<uint32_t>(c->seed);
+        p.key1 = static_cast<uint32_t>(c->seed >> 32);
+        const int n_chains = static_cast<int>(k.samples.size()) * k.C;
+        return timed_launch(c, p.energy_only ? kEnergyOnly : kResidentKind,
+                            [&] { return launch_resident_step(p, n_chains, c->stream); });
+    }
     if (k.lanes == 1) {
         uint64_t hb = hb0;
         for (int n = 0; n < total; ++n) {
@@ -616,7 +653,7 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     // lattice classes (same L, T and mapping), swept by the same launches
     {
         std::map<std::tuple<int, int, int>, std::vector<int>> groups;
-        for (int s = 0; s < P.S; ++s) groups[{P.L[s], P.T[s], P.lanes[s]}].push_back(s);
+        for (int s = 0; s < P.S; ++s) groups[{P.L[s], P.T[s], P.mapping[s]}].push_back(s);
         int *dsamp = reinterpret_cast<int *>(w + P.off_classes);
         int *ditems = reinterpret_cast<int *>(w + P.off_items);
         int at = 0, at_items = 0;
@@ -624,7 +661,8 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
             LatticeClass k;
             k.L = std::get<0>(g.first);
             k.T = std::get<1>(g.first);
-            k.lanes = std::get<2>(g.first);
+            k.mapping = std::get<2>(g.first);
+            k.lanes = k.mapping == kChainLanes ? 64 : 1;
             k.C = P.R * k.T;
             const int H = k.L * k.L * k.L / 2;
             k.samples = g.second;
@@ -632,7 +670,9 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
             PT_HIP(hipMemcpy(k.d_samples, g.second.data(), g.second.size() * sizeof(int),
                              hipMemcpyHostToDevice));
             at += static_cast<int>(g.second.size());
-            if (k.lanes == 1) {
+            if (k.mapping == kResident) {
+                k.blocks = 1;
+            } else if (k.mapping == kSiteLanes) {
                 k.blocks = (H + kSweepBlock - 1) / kSweepBlock;
                 k.G = choose_group(H, k.C, static_cast<int>(g.second.size()));
             } else {
@@ -875,8 +915,10 @@ pt_status pt_profile(pt_ctx *c, int enable)
     if (st != PT_OK) return st;
     if ((st = drain_events(c)) != PT_OK) return st;
     c->profiling = enable != 0;
-    c->prof_launches[0] = c->prof_launches[1] = 0;
-    c->prof_ms[0] = c->prof_ms[1] = 0.0;
+    for (int q = 0; q < 3; ++q) {
+        c->prof_launches[q] = 0;
+        c->prof_ms[q] = 0.0;
+    }
     return PT_OK;
 }
 
@@ -884,7 +926,8 @@ pt_status pt_kernel_time(pt_ctx *c, int kind, uint64_t *launches, double *ms)
 {
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
-    if (kind != PT_K_OVERRELAX && kind != PT_K_HEATBATH) return fail(PT_EINVAL, "unknown kernel kind");
+    if (kind != PT_K_OVERRELAX && kind != PT_K_HEATBATH && kind != PT_K_RESIDENT)
+        return fail(PT_EINVAL, "unknown kernel kind");
     if ((st = drain_events(c)) != PT_OK) return st;
     if (launches) *launches = c->prof_launches[kind];
     if (ms) *ms = c->prof_ms[kind];

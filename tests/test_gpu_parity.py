@@ -23,7 +23,8 @@ def _gpu():
     ptsg.load_library()
 
 
-MAPPINGS = {"site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES}
+MAPPINGS = {"site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES,
+            "resident": ptsg.PT_F_RESIDENT}
 
 
 def _ctx(Ls, temps, R, seed, cpl=None, flags=0):
@@ -248,12 +249,13 @@ def test_mappings_bit_identical():
                      [ptsg.pt_get_perm(ctx, s, r) for s in range(2) for r in range(R)],
                      ptsg.pt_get_energy(ctx))
         ptsg.pt_free(ctx)
-    for a, b in zip(out["site"][0], out["chain"][0]):
-        np.testing.assert_array_equal(a, b)
-    for a, b in zip(out["site"][1], out["chain"][1]):
-        np.testing.assert_array_equal(a, b)
-    for a, b in zip(out["site"][2], out["chain"][2]):
-        np.testing.assert_allclose(a, b, rtol=1e-12)
+    for other in ("chain", "resident"):
+        for a, b in zip(out["site"][0], out[other][0]):
+            np.testing.assert_array_equal(a, b, err_msg=other)
+        for a, b in zip(out["site"][1], out[other][1]):
+            np.testing.assert_array_equal(a, b, err_msg=other)
+        for a, b in zip(out["site"][2], out[other][2]):
+            np.testing.assert_allclose(a, b, rtol=1e-12, err_msg=other)
 
 
 def test_deterministic_replay():
