@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--preset", default="L64x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel of a step instead of replaying a captured hipGraph")
     ap.add_argument("--mapping", choices=("auto", "site", "chain", "resident"), default="auto",
                     help="sweep kernel mapping (auto: resident for L <= 16, else chain lanes when "
                          "a sample's chains fill 64-lane waves to >= 90%%)")
@@ -131,6 +133,8 @@ def main():
     else:
         waves = (C_sample + 63) // 64
         mapping = "chain" if L <= 128 and 10 * C_sample >= 9 * 64 * waves else "site"
+    if not args.no_graphs:
+        flags |= ptsg.PT_F_GRAPHS
     ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
     n_chains = ctx.n_chains
     N = L ** 3
@@ -144,9 +148,7 @@ def main():
 
     for t in range(args.warmup):
         step(t)
-    torch.cuda.synchronize()
     ptsg.pt_sync(ctx)
-    ptsg.pt_profile(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for t in range(args.steps):
@@ -154,6 +156,13 @@ def main():
     ptsg.pt_sync(ctx)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # Kernel durations: the same steps again with the dispatches stamping HIP
+    # events (kernel start and end, on the library's stream); these steps run
+    # without the captured graph and are not part of `value`.
+    ptsg.pt_profile(ctx, True)
+    for t in range(args.steps):
+        step(t)
+    ptsg.pt_sync(ctx)
     n_or_launch, or_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_OVERRELAX)
     n_hb_launch, hb_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_HEATBATH)
     n_rs_launch, rs_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_RESIDENT)
@@ -210,6 +219,7 @@ def main():
             "L": L, "samples": len(Ls), "temperatures": len(temps[0]), "replicas": R,
             "spin_updates_per_step": su_per_step,
             "mapping": mapping + " lanes",
+            "graphs": not args.no_graphs,
         },
         "roofline": roof,
         "heatbath_avg_launch_ms": round(hb_ms / max(1, n_hb_launch), 4),

@@ -127,7 +127,12 @@ typedef struct {
 enum {
     PT_F_SITE_LANES = 1u,
     PT_F_CHAIN_LANES = 2u,
-    PT_F_RESIDENT = 4u
+    PT_F_RESIDENT = 4u,
+    /* Capture the launch sequence of pt_step(n_hb, n_or) in a hipGraph the
+     * first time each (n_hb, n_or) is used and replay it afterwards (the
+     * Philox counters live in device memory, so replays are exact).  Steps
+     * taken while kernel timing is enabled run without the graph. */
+    PT_F_GRAPHS = 8u
 };
 
 /* One sample (the single-lattice form of the API).  Equivalent to

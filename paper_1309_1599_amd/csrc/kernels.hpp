@@ -21,6 +21,7 @@
 //          three forward bond matrices of site i are floats 27i .. 27i+26.
 //  chains  global chain id = chain_base[sample] + rep*T + j, j = start slot.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,7 +65,9 @@ struct SweepParams {
     int L, H, C, G, T;           // lattice, N/2, chains/sample, chains/workgroup, slots
     int n_tiles, per;            // site blocks per sample; blocks per XCD (grid = 8*per)
     int colour;
-    uint32_t hb_sweep, key0, key1;
+    const uint32_t *counters;    // device [0]: heat-bath sweeps done, [1]: PT passes done
+    uint32_t hb_offset;          // this sweep's index within the step
+    uint32_t key0, key1;
 };
 
 // Chain-lane mapping (one wave = 64 chains of one sample at one site).
@@ -83,7 +86,9 @@ struct ClParams {
     int split;                   // waves per packed row (divides L/2)
     int n_tiles, per;            // workgroups of rows per item; per XCD (grid = 8*per)
     int colour;
-    uint32_t hb_sweep, key0, key1;
+    const uint32_t *counters;    // device [0]: heat-bath sweeps done, [1]: PT passes done
+    uint32_t hb_offset;          // this sweep's index within the step
+    uint32_t key0, key1;
 };
 
 // Lattice-resident mapping: one workgroup per chain, spins in LDS for a step.
@@ -97,7 +102,8 @@ struct RsParams {
     double *E;
     int L, H, C, T;
     int n_hb, n_or, energy_only;
-    uint32_t hb_sweep, key0, key1;
+    const uint32_t *counters;    // device [0]: heat-bath sweeps done before this step
+    uint32_t key0, key1;
 };
 
 struct SwapParams {
@@ -108,7 +114,8 @@ struct SwapParams {
     const double *betas;         // [sample][T] by slot
     const int *chain_base, *perm_base, *beta_base, *n_temps;
     int n_samples, R;
-    uint32_t pass, key0, key1;
+    const uint32_t *counters;    // device [1]: PT passes done (the pass counter)
+    uint32_t key0, key1;
 };
 
 struct EnergyParams {
@@ -135,14 +142,35 @@ struct MeasParams {
     void *out;                   // device pt_meas[n_records]
 };
 
+// Optional kernel timing: when `start` is set, the dispatch itself stamps the
+// two events at the kernel's start and end (the time a profiler reports).
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+template <typename Kernel, typename... Args>
+hipError_t launch_kernel(Kernel kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t st,
+                         const LaunchTiming &t, Args... args)
+{
+    if (t.start)
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, st, t.start, t.stop, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+    return hipGetLastError();
+}
+
 hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_samples,
-                             hipStream_t st);
+                             hipStream_t st, const LaunchTiming &t = {});
 hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items,
-                                hipStream_t st);
-hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st);
+                                hipStream_t st, const LaunchTiming &t = {});
+hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st,
+                                const LaunchTiming &t = {});
 int rs_block(int L);
 hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st);
 hipError_t launch_swap(const SwapParams &p, hipStream_t st);
+// counters[0] += d_hb, counters[1] += d_pt (one lane; keeps replays of a
+// captured step on fresh Philox counters)
+hipError_t launch_advance_counters(uint32_t *counters, uint32_t d_hb, uint32_t d_pt, hipStream_t st);
 hipError_t launch_init_spins(float *spins, int64_t spin_base, int lanes, int L, int C, int T,
                              int sample, uint32_t key0, uint32_t key1, hipStream_t st);
 int cl_blocks(int L, int split);

@@ -64,7 +64,8 @@ struct Plan {
     int total_perm = 0, n_items = 0;
     size_t off_spins = 0, off_cpls = 0, off_cpl6 = 0, off_slot = 0, off_beta_of = 0, off_E = 0,
            off_perm = 0, off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0,
-           off_mpart = 0, off_meas = 0, off_classes = 0, off_items = 0, off_stage = 0, bytes = 0;
+           off_mpart = 0, off_meas = 0, off_classes = 0, off_items = 0, off_stage = 0, off_counters = 0,
+           bytes = 0;
 };
 
 // Chain-lane launches keep the working set of one batch of (sample, group)
@@ -217,6 +218,7 @@ Plan make_plan(const pt_batch_desc *d)
     p.off_classes = take(sizeof(int) * p.S);
     p.off_items = take(sizeof(int) * 2 * std::max(1, p.n_items));
     p.off_stage = take(sizeof(float) * 3 * static_cast<size_t>(p.Lmax) * p.Lmax * p.Lmax);
+    p.off_counters = take(2 * sizeof(uint32_t));
     p.bytes = o;
     return p;
 }
@@ -241,6 +243,10 @@ struct pt_ctx {
     double *E = nullptr, *betas = nullptr, *epart = nullptr, *twid = nullptr, *mpart = nullptr;
     pt_meas *meas = nullptr;
     float *stage = nullptr;           // one chain in canonical [N][3] order
+    uint32_t *counters = nullptr;     // device: heat-bath sweeps, PT passes
+    bool use_graphs = false;
+    hipStream_t capture_stream = nullptr;
+    std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
     int *d_L = nullptr, *d_T = nullptr, *d_chain_base = nullptr, *d_perm_base = nullptr,
         *d_beta_base = nullptr, *d_twid_base = nullptr, *d_lanes = nullptr;
     int64_t *d_spin_base = nullptr, *d_cpls_base = nullptr, *d_cpl6_base = nullptr;
@@ -254,7 +260,7 @@ struct pt_ctx {
 
 namespace {
 
-SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour, uint32_t hb_sweep)
+SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour, uint32_t hb_offset)
 {
     SweepParams p{};
     p.spins = c->spins;
@@ -275,13 +281,14 @@ SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour, uint32_t 
     p.n_tiles = k.blocks;
     p.per = (k.blocks + 7) / 8;
     p.colour = colour;
-    p.hb_sweep = hb_sweep;
+    p.counters = c->counters;
+    p.hb_offset = hb_offset;
     p.key0 = static_cast<uint32_t>(c->seed);
     p.key1 = static_cast<uint32_t>(c->seed >> 32);
     return p;
 }
 
-ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour, uint32_t hb_sweep)
+ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour, uint32_t hb_offset)
 {
     ClParams p{};
     p.spins = c->spins;
@@ -302,7 +309,8 @@ ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour,
     p.n_tiles = k.blocks;
     p.per = (k.blocks + 7) / 8;
     p.colour = colour;
-    p.hb_sweep = hb_sweep;
+    p.counters = c->counters;
+    p.hb_offset = hb_offset;
     p.key0 = static_cast<uint32_t>(c->seed);
     p.key1 = static_cast<uint32_t>(c->seed >> 32);
     return p;
@@ -337,12 +345,14 @@ pt_status drain_events(pt_ctx *c)
 
 constexpr int kResidentKind = 3;  // profiling tag of whole-step resident launches
 
-// Bracket one sweep launch with profiling events when enabled.
+// Launch one sweep kernel; when profiling, the dispatch stamps a pair of
+// events at the kernel's start and end.
 template <class Launch>
 pt_status timed_launch(pt_ctx *c, int kind, Launch launch)
 {
     const bool timed = c->profiling && kind != kEnergyOnly;
     Event ev;
+    LaunchTiming t;
     if (timed) {
         if (c->pending.size() >= 4096) {
             pt_status st = drain_events(c);
@@ -350,14 +360,13 @@ pt_status timed_launch(pt_ctx *c, int kind, Launch launch)
         }
         pt_status st = get_event(c, ev);
         if (st != PT_OK) return st;
-        PT_HIP(hipEventRecord(ev.a, c->stream));
+        t.start = ev.a;
+        t.stop = ev.b;
     }
-    PT_HIP(launch());
-    if (timed) {
-        PT_HIP(hipEventRecord(ev.b, c->stream));
+    PT_HIP(launch(t));
+    if (timed)
         c->pending.push_back({kind == kOverrelax ? PT_K_OVERRELAX
                               : kind == kHeatbath ? PT_K_HEATBATH : PT_K_RESIDENT, ev});
-    }
     return PT_OK;
 }
 
@@ -375,10 +384,10 @@ pt_status finalize_energies(pt_ctx *c, const LatticeClass &k)
     return PT_OK;
 }
 
-// The sweeps of one class: `kinds` lists the sweep kinds in order; the
-// heat-bath sweep n of the list uses counter hb0 + n.  The energy partials
-// are fused into the last half-sweep.
-pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &kinds, uint64_t hb0)
+// The sweeps of one class: `kinds` lists the sweep kinds in order; the n-th
+// heat-bath sweep of the list uses Philox counter (device heat-bath count) + n.
+// The energy partials are fused into the last half-sweep.
+pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &kinds)
 {
     const int total = static_cast<int>(kinds.size());
     if (total == 0) return PT_OK;
@@ -402,22 +411,24 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
         p.energy_only = kinds[0] == kEnergyOnly;
         p.n_hb = p.energy_only ? 0 : static_cast<int>(std::count(kinds.begin(), kinds.end(), kHeatbath));
         p.n_or = p.energy_only ? 1 : total - p.n_hb;
-        p.hb_sweep = static_cast<uint32_t>(hb0);
+        p.counters = c->counters;
         p.key0 = static_cast<uint32_t>(c->seed);
         p.key1 = static_cast<uint32_t>(c->seed >> 32);
         const int n_chains = static_cast<int>(k.samples.size()) * k.C;
         return timed_launch(c, p.energy_only ? kEnergyOnly : kResidentKind,
-                            [&] { return launch_resident_step(p, n_chains, c->stream); });
+                            [&](const LaunchTiming &t) { return launch_resident_step(p, n_chains, c->stream, t); });
     }
     if (k.lanes == 1) {
-        uint64_t hb = hb0;
+        uint32_t hb = 0;
         for (int n = 0; n < total; ++n) {
             const int kind = kinds[n];
             for (int colour = 0; colour < 2; ++colour) {
                 const bool energy = n == total - 1 && colour == 1;
-                const SweepParams p = sweep_params(c, k, colour, static_cast<uint32_t>(hb));
+                const SweepParams p = sweep_params(c, k, colour, hb);
                 const int ns = static_cast<int>(k.samples.size());
-                st = timed_launch(c, kind, [&] { return launch_half_sweep(kind, energy, p, ns, c->stream); });
+                st = timed_launch(c, kind, [&](const LaunchTiming &t) {
+                    return launch_half_sweep(kind, energy, p, ns, c->stream, t);
+                });
                 if (st != PT_OK) return st;
             }
             if (kind == kHeatbath) ++hb;
@@ -427,13 +438,15 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
         const int n_items = static_cast<int>(k.items.size() / 2);
         for (int first = 0; first < n_items; first += k.batch) {
             const int cnt = std::min(k.batch, n_items - first);
-            uint64_t hb = hb0;
+            uint32_t hb = 0;
             for (int n = 0; n < total; ++n) {
                 const int kind = kinds[n];
                 for (int colour = 0; colour < 2; ++colour) {
                     const bool energy = n == total - 1 && colour == 1;
-                    const ClParams p = cl_params(c, k, first, colour, static_cast<uint32_t>(hb));
-                    st = timed_launch(c, kind, [&] { return launch_cl_half_sweep(kind, energy, p, cnt, c->stream); });
+                    const ClParams p = cl_params(c, k, first, colour, hb);
+                    st = timed_launch(c, kind, [&](const LaunchTiming &t) {
+                        return launch_cl_half_sweep(kind, energy, p, cnt, c->stream, t);
+                    });
                     if (st != PT_OK) return st;
                 }
                 if (kind == kHeatbath) ++hb;
@@ -447,7 +460,7 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
 pt_status refresh_energies(pt_ctx *c)
 {
     for (const auto &k : c->classes) {
-        pt_status st = sweep_class(c, k, {kEnergyOnly}, 0);
+        pt_status st = sweep_class(c, k, {kEnergyOnly});
         if (st != PT_OK) return st;
     }
     return PT_OK;
@@ -562,6 +575,12 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     c->mpart = reinterpret_cast<double *>(w + P.off_mpart);
     c->meas = reinterpret_cast<pt_meas *>(w + P.off_meas);
     c->stage = reinterpret_cast<float *>(w + P.off_stage);
+    c->counters = reinterpret_cast<uint32_t *>(w + P.off_counters);
+    c->use_graphs = (d->flags & PT_F_GRAPHS) != 0;
+    {
+        const uint32_t zero[2] = {0u, 0u};
+        PT_HIP(hipMemcpy(c->counters, zero, sizeof(zero), hipMemcpyHostToDevice));
+    }
     {
         char *m = w + P.off_meta;
         c->d_spin_base = reinterpret_cast<int64_t *>(m);
@@ -722,15 +741,53 @@ pt_status pt_init(pt_ctx **ctx, int L, const float *couplings, const double *tem
     return pt_init_batch(ctx, &d);
 }
 
+// Queue one step on `st`: every class's sweeps, then advance the device
+// heat-bath counter.
+static pt_status queue_step(pt_ctx *c, int n_hb, int n_or)
+{
+    std::vector<int> kinds(n_hb, kHeatbath);
+    kinds.insert(kinds.end(), n_or, kOverrelax);
+    pt_status st;
+    for (const auto &k : c->classes)
+        if ((st = sweep_class(c, k, kinds)) != PT_OK) return st;
+    if (n_hb > 0) PT_HIP(launch_advance_counters(c->counters, static_cast<uint32_t>(n_hb), 0u, c->stream));
+    return PT_OK;
+}
+
 pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
 {
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
     if (n_hb < 0 || n_or < 0) return fail(PT_EINVAL, "n_hb and n_or must be >= 0");
-    std::vector<int> kinds(n_hb, kHeatbath);
-    kinds.insert(kinds.end(), n_or, kOverrelax);
-    for (const auto &k : c->classes)
-        if ((st = sweep_class(c, k, kinds, c->hb_sweeps)) != PT_OK) return st;
+    if (n_hb + n_or == 0) return PT_OK;
+    if (!c->use_graphs || c->profiling) {
+        if ((st = queue_step(c, n_hb, n_or)) != PT_OK) return st;
+    } else {
+        // A step's launch sequence depends only on (n_hb, n_or): capture it
+        // once on a private stream, then replay it on the context's stream.
+        auto it = c->step_graphs.find({n_hb, n_or});
+        if (it == c->step_graphs.end()) {
+            if (!c->capture_stream) PT_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+            hipStream_t user = c->stream;
+            c->stream = c->capture_stream;
+            hipGraph_t graph = nullptr;
+            PT_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
+            st = queue_step(c, n_hb, n_or);
+            const hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+            c->stream = user;
+            if (st != PT_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(PT_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) return fail(PT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            it = c->step_graphs.emplace(std::make_pair(n_hb, n_or), exec).first;
+        }
+        PT_HIP(hipGraphLaunch(it->second, c->stream));
+    }
     c->hb_sweeps += n_hb;
     return PT_OK;
 }
@@ -751,10 +808,11 @@ pt_status pt_swap(pt_ctx *c)
     p.n_temps = c->d_T;
     p.n_samples = c->plan.S;
     p.R = c->plan.R;
-    p.pass = static_cast<uint32_t>(c->pt_passes);
+    p.counters = c->counters;
     p.key0 = static_cast<uint32_t>(c->seed);
     p.key1 = static_cast<uint32_t>(c->seed >> 32);
     PT_HIP(launch_swap(p, c->stream));
+    PT_HIP(launch_advance_counters(c->counters, 0u, 1u, c->stream));
     c->pt_passes += 1;
     return PT_OK;
 }
@@ -944,6 +1002,8 @@ void pt_free(pt_ctx *c)
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
+    for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.second);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     delete c;
 }

@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
         }
         const double e = update<KIND>(g, A, rsrc_of(j), off, H4, active,
                                       static_cast<uint32_t>(nb.site), static_cast<uint32_t>(s),
-                                      ctr3, P.hb_sweep, P.key0, P.key1, beta);
+                                      ctr3, P.counters[0] + P.hb_offset, P.key0, P.key1, beta);
         if constexpr (ENERGY) {
             // every bond has exactly one end of colour 1: E = -sum_{colour 1} s.h
             const double w = wave_sum(active ? e : 0.0);
@@ -238,7 +238,21 @@ __global__ void chain_io_kernel(float *spins, int64_t base, int lanes, int L, in
     }
 }
 
+__global__ void advance_counters_kernel(uint32_t *counters, uint32_t d_hb, uint32_t d_pt)
+{
+    if (threadIdx.x == 0) {
+        counters[0] += d_hb;
+        counters[1] += d_pt;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_advance_counters(uint32_t *counters, uint32_t d_hb, uint32_t d_pt, hipStream_t st)
+{
+    hipLaunchKernelGGL(advance_counters_kernel, dim3(1), dim3(64), 0, st, counters, d_hb, d_pt);
+    return hipGetLastError();
+}
 
 hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, float *canon,
                            bool to_canon, hipStream_t st)
@@ -250,18 +264,19 @@ hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, 
 }
 
 hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_samples,
-                             hipStream_t st)
+                             hipStream_t st,
+                             const LaunchTiming &t)
 {
     const dim3 grid(kXcds * p.per, (p.C + p.G - 1) / p.G, n_samples);
     const dim3 block(kSweepBlock);
     if (kind == kOverrelax) {
-        if (energy) hipLaunchKernelGGL((half_sweep_kernel<kOverrelax, true>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((half_sweep_kernel<kOverrelax, false>), grid, block, 0, st, p);
+        if (energy) return launch_kernel(half_sweep_kernel<kOverrelax, true>, grid, block, 0, st, t, p);
+        else return launch_kernel(half_sweep_kernel<kOverrelax, false>, grid, block, 0, st, t, p);
     } else if (kind == kHeatbath) {
-        if (energy) hipLaunchKernelGGL((half_sweep_kernel<kHeatbath, true>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((half_sweep_kernel<kHeatbath, false>), grid, block, 0, st, p);
+        if (energy) return launch_kernel(half_sweep_kernel<kHeatbath, true>, grid, block, 0, st, t, p);
+        else return launch_kernel(half_sweep_kernel<kHeatbath, false>, grid, block, 0, st, t, p);
     } else {
-        hipLaunchKernelGGL((half_sweep_kernel<kEnergyOnly, true>), grid, block, 0, st, p);
+        return launch_kernel(half_sweep_kernel<kEnergyOnly, true>, grid, block, 0, st, t, p);
     }
     return hipGetLastError();
 }

@@ -78,9 +78,10 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
     // the constant address space lets wave-uniform loads become scalar loads.
     const CFloat *M = (const CFloat *)(P.cpls + P.cpls_base[s]);
 
-    uint32_t ctr3 = 0;
+    uint32_t ctr3 = 0, hb_sweep = 0;
     float beta = 0.0f;
     if constexpr (KIND == kHeatbath) {
+        hb_sweep = P.counters[0] + P.hb_offset;
         const int chain = P.chain_base[s] + (lane_on ? j : 0);
         ctr3 = ctr_word3(0u, static_cast<uint32_t>(P.slot_of[chain]), static_cast<uint32_t>(j / P.T));
         beta = P.beta_of[chain];
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
             }, h);
             float sx, sy, sz;
             if constexpr (KIND == kHeatbath) {
-                const uint4 w = philox10(make_uint4(static_cast<uint32_t>(t.site), P.hb_sweep,
+                const uint4 w = philox10(make_uint4(static_cast<uint32_t>(t.site), hb_sweep,
                                                     static_cast<uint32_t>(s), ctr3),
                                          P.key0, P.key1);
                 heatbath(sx, sy, sz, h[0], h[1], h[2], beta, unit23(w.x), unit23(w.y));
@@ -206,18 +207,19 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
 
 int cl_blocks(int L, int split) { return (L * L * split + kClWaves - 1) / kClWaves; }
 
-hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items, hipStream_t st)
+hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items, hipStream_t st,
+                                const LaunchTiming &t)
 {
     const dim3 grid(kXcds * p.per, 1, n_items);
     const dim3 block(kClBlock);
     if (kind == kOverrelax) {
-        if (energy) hipLaunchKernelGGL((cl_half_sweep_kernel<kOverrelax, true>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((cl_half_sweep_kernel<kOverrelax, false>), grid, block, 0, st, p);
+        if (energy) return launch_kernel(cl_half_sweep_kernel<kOverrelax, true>, grid, block, 0, st, t, p);
+        else return launch_kernel(cl_half_sweep_kernel<kOverrelax, false>, grid, block, 0, st, t, p);
     } else if (kind == kHeatbath) {
-        if (energy) hipLaunchKernelGGL((cl_half_sweep_kernel<kHeatbath, true>), grid, block, 0, st, p);
-        else hipLaunchKernelGGL((cl_half_sweep_kernel<kHeatbath, false>), grid, block, 0, st, p);
+        if (energy) return launch_kernel(cl_half_sweep_kernel<kHeatbath, true>, grid, block, 0, st, t, p);
+        else return launch_kernel(cl_half_sweep_kernel<kHeatbath, false>, grid, block, 0, st, t, p);
     } else {
-        hipLaunchKernelGGL((cl_half_sweep_kernel<kEnergyOnly, true>), grid, block, 0, st, p);
+        return launch_kernel(cl_half_sweep_kernel<kEnergyOnly, true>, grid, block, 0, st, t, p);
     }
     return hipGetLastError();
 }

@@ -57,11 +57,12 @@ __global__ __launch_bounds__(kRsMaxBlock) void resident_step_kernel(RsParams P)
     }
     const float *cpl = P.cpl + P.cpl_base[s];
     const int total = P.n_hb + P.n_or;
+    const uint32_t hb0 = P.counters[0];
     double e_acc = 0.0;
     __syncthreads();
     for (int n = 0; n < total; ++n) {
         const int kind = P.energy_only ? kEnergyOnly : (n < P.n_hb ? kHeatbath : kOverrelax);
-        const uint32_t hb_sweep = P.hb_sweep + static_cast<uint32_t>(n);
+        const uint32_t hb_sweep = hb0 + static_cast<uint32_t>(n);
         for (int c = 0; c < 2; ++c) {
             const float *oth = lds + (1 - c) * 3 * H;
             float *own = lds + c * 3 * H;
@@ -126,11 +127,10 @@ int rs_block(int L)
     return std::min(kRsMaxBlock, (H + 63) / 64 * 64);
 }
 
-hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st)
+hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st, const LaunchTiming &t)
 {
-    const size_t lds = sizeof(float) * 6 * static_cast<size_t>(p.H);
-    hipLaunchKernelGGL(resident_step_kernel, dim3(n_chains), dim3(rs_block(p.L)), lds, st, p);
-    return hipGetLastError();
+    const uint32_t lds = static_cast<uint32_t>(sizeof(float) * 6 * static_cast<size_t>(p.H));
+    return launch_kernel(resident_step_kernel, dim3(n_chains), dim3(rs_block(p.L)), lds, st, t, p);
 }
 
 }  // namespace ptsg

@@ -24,10 +24,11 @@ __global__ void swap_kernel(SwapParams P)
     const double *beta = P.betas + P.beta_base[s];
     const int cb = P.chain_base[s] + r * T;
     const double *E = P.E + cb;
+    const uint32_t pass = P.counters[1];
     for (int k = 0; k + 1 < T; ++k) {
         const int a = perm[k], b = perm[k + 1];
         const double delta = (beta[k] - beta[k + 1]) * (E[a] - E[b]);
-        const uint4 w = philox10(make_uint4(static_cast<uint32_t>(k), P.pass,
+        const uint4 w = philox10(make_uint4(static_cast<uint32_t>(k), pass,
                                             static_cast<uint32_t>(s),
                                             ctr_word3(1u, 0u, static_cast<uint32_t>(r))),
                                  P.key0, P.key1);

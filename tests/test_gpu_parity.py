@@ -285,3 +285,28 @@ def test_error_paths():
     assert e.value.status == ptsg.PT_EINVAL
     with pytest.raises(ptsg.PtError):
         ptsg.pt_get_spins(ctx, 0, 0, 5)
+
+
+@pytest.mark.parametrize("L,T,R", [(8, 4, 2), (20, 32, 2), (20, 3, 2)])
+def test_graph_replays_match_eager(L, T, R):
+    """A captured step replayed several times (with host reads between the
+    replays) gives exactly the eager result: resident, chain-lane and
+    site-lane classes respectively."""
+    seed = 880 + L + T
+    temps = [inputs.geometric_temps(0.7, 1.5, T)]
+    cpl = [inputs.gaussian_couplings(L, seed)]
+    eager = ptsg.pt_init_batch([L], cpl, temps, R, seed)
+    graph = ptsg.pt_init_batch([L], cpl, temps, R, seed, flags=ptsg.PT_F_GRAPHS)
+    for step in range(4):
+        for ctx in (eager, graph):
+            ptsg.pt_step(ctx, 1, 3)
+            ptsg.pt_swap(ctx)
+        assert ptsg.pt_get_counters(eager) == ptsg.pt_get_counters(graph) == (step + 1, step + 1)
+        for r in range(R):
+            np.testing.assert_array_equal(ptsg.pt_get_perm(eager, 0, r), ptsg.pt_get_perm(graph, 0, r))
+            for k in (0, T - 1):
+                np.testing.assert_array_equal(ptsg.pt_get_spins(eager, 0, r, k),
+                                              ptsg.pt_get_spins(graph, 0, r, k))
+        np.testing.assert_array_equal(ptsg.pt_get_energy(eager)[0], ptsg.pt_get_energy(graph)[0])
+    ptsg.pt_free(eager)
+    ptsg.pt_free(graph)
