@@ -1,12 +1,12 @@
 """Benchmark: picoseconds per spin update of the whole Monte Carlo step on
-one MI355X, with the HBM roofline of the dominant kernel and the FP64 oracle
+one MI355X, with the roofline of the dominant kernel and the FP64 oracle
 timed beside it.
 
-Workload (default): L = 64, 8 disorder samples, 32 temperatures x 4
-replicas = 1024 chains, Gaussian 3x3 couplings; one step = 1 heat-bath +
-64 overrelaxation sweeps + 1 tempering pass, with the overlap / chirality /
-Schwinger-Dyson measurement every 10 steps.  Inputs are resident in HBM
-before the timed region.
+Workload (default, preset L64x8): L = 64, 8 disorder samples, 32
+temperatures x 4 replicas = 1024 chains, Gaussian 3x3 couplings; one step =
+1 heat-bath + 64 overrelaxation sweeps + 1 tempering pass, with the overlap /
+chirality / Schwinger-Dyson measurement every 10 steps.  Inputs are resident
+in HBM before the timed region.
 
 Prints one JSON line.
 """
@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz
-FLOPS_PER_SU = 138
+FLOPS_PER_SU = 138          # overrelaxation update: 54-term field, reflection, renormalisation
 METRIC = "ps per spin update (all chains) & HBM roofline %, batched FP32 vs plain FP64"
 KERNEL_SOURCES = ["paper_1309_1599_amd/csrc/sweep.hip", "paper_1309_1599_amd/csrc/sweep_cl.hip",
                   "paper_1309_1599_amd/csrc/sweep_rs.hip",
@@ -56,7 +56,7 @@ def pmc_traffic(expected_hash):
     return float(b.group(1))
 
 
-def cpu_baseline(L, cpl, temps, seed, n_chains=64, n_or=12):
+def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample of
     the same workload: n_chains chains of sample 0, one heat-bath sweep,
     n_or overrelaxation sweeps and one energy evaluation each; the step's
@@ -82,7 +82,63 @@ def cpu_baseline(L, cpl, temps, seed, n_chains=64, n_or=12):
     per_hb = t_hb / (n_chains * N)
     per_or = t_or / (n_chains * n_or * N)
     per_e = t_e / n_chains
-    return per_hb, per_or, per_e, t_hb + t_or + t_e
+    step_s = (n_hb * per_hb + n_or_step * per_or) * N + per_e
+    return {
+        "value": round(step_s / ((n_hb + n_or_step) * N) * 1e12, 1),
+        "unit": "ps/SU",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n_chains} chains of sample 0 at L={L}: 1 heat-bath + {n_or} overrelaxation sweeps "
+                  f"and one energy each ({t_hb + t_or + t_e:.1f} s), composed to the {n_hb} HB + "
+                  f"{n_or_step} OR step",
+    }
+
+
+def auto_mapping(L, C):
+    if L <= 16:
+        return "resident"
+    waves = (C + 63) // 64
+    return "chain" if L <= 128 and 10 * C >= 9 * 64 * waves else "site"
+
+
+def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, warmup, timing=True):
+    """Time `steps` steps after `warmup`; optionally a second pass with
+    kernel-stamped events for the kernel durations."""
+    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
+    su_per_step = sum((n_hb + n_or) * R * len(t) * L ** 3 for L, t in zip(Ls, temps))
+
+    def step(t):
+        ptsg.pt_step(ctx, n_hb, n_or)
+        ptsg.pt_swap(ctx)
+        if every and (t + 1) % every == 0:
+            ptsg.pt_measure(ctx, ptsg.PT_M_ALL)
+
+    for t in range(warmup):
+        step(t)
+    ptsg.pt_sync(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        step(t)
+    ptsg.pt_sync(ctx)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = None
+    if timing:
+        # Kernel durations: the same steps again with the dispatches stamping
+        # HIP events at kernel start and end on the library's stream; these
+        # steps run without a captured graph and are not part of `value`.
+        ptsg.pt_profile(ctx, True)
+        for t in range(steps):
+            step(t)
+        ptsg.pt_sync(ctx)
+        kt = {k: ptsg.pt_kernel_time(ctx, v) for k, v in
+              (("or", ptsg.PT_K_OVERRELAX), ("hb", ptsg.PT_K_HEATBATH), ("rs", ptsg.PT_K_RESIDENT))}
+        ptsg.pt_profile(ctx, False)
+    ptsg.pt_free(ctx)
+    del ctx
+    torch.cuda.empty_cache()
+    return wall, su_per_step, kt
 
 
 def main():
@@ -92,6 +148,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--preset", default="L64x8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain single-chain reference")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel of a step instead of replaying a captured hipGraph")
     ap.add_argument("--mapping", choices=("auto", "site", "chain", "resident"), default="auto",
@@ -111,11 +168,17 @@ def main():
     p = inputs.PRESETS[args.preset]
     Ls, cpl, temps, R, seed = inputs.preset_inputs(args.preset)
     n_hb = p["n_hb"]
-    n_or_of = (lambda L: L) if p["n_or"] is None else (lambda L: p["n_or"])
-    assert len(set(Ls)) == 1, "bench times one lattice size per run"
-    L = Ls[0]
-    n_or = n_or_of(L)
+    mixed = len(set(Ls)) > 1
+    # a mixed batch shares one step: 1 HB + 16 OR + PT
+    n_or = 16 if p["n_or"] is None and mixed else (Ls[0] if p["n_or"] is None else p["n_or"])
     every = p["measure_every"]
+    flags = {"auto": 0, "site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES,
+             "resident": ptsg.PT_F_RESIDENT}[args.mapping]
+    if not args.no_graphs:
+        flags |= ptsg.PT_F_GRAPHS
+    L = Ls[0]
+    C = R * len(temps[0])
+    mapping = args.mapping if args.mapping != "auto" else auto_mapping(L, C)
 
     # plain copy of a known size: calibrates the rocprofv3 byte counters
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -123,61 +186,20 @@ def main():
     b.copy_(a)
     del a, b
 
-    flags = {"auto": 0, "site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES,
-             "resident": ptsg.PT_F_RESIDENT}[args.mapping]
-    C_sample = R * len(temps[0])
-    if args.mapping != "auto":
-        mapping = args.mapping
-    elif L <= 16:
-        mapping = "resident"
-    else:
-        waves = (C_sample + 63) // 64
-        mapping = "chain" if L <= 128 and 10 * C_sample >= 9 * 64 * waves else "site"
-    if not args.no_graphs:
-        flags |= ptsg.PT_F_GRAPHS
-    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
-    n_chains = ctx.n_chains
-    N = L ** 3
-    su_per_step = (n_hb + n_or) * n_chains * N
-
-    def step(t):
-        ptsg.pt_step(ctx, n_hb, n_or)
-        ptsg.pt_swap(ctx)
-        if every and (t + 1) % every == 0:
-            ptsg.pt_measure(ctx, ptsg.PT_M_ALL)
-
-    for t in range(args.warmup):
-        step(t)
-    ptsg.pt_sync(ctx)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(args.steps):
-        step(t)
-    ptsg.pt_sync(ctx)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # Kernel durations: the same steps again with the dispatches stamping HIP
-    # events (kernel start and end, on the library's stream); these steps run
-    # without the captured graph and are not part of `value`.
-    ptsg.pt_profile(ctx, True)
-    for t in range(args.steps):
-        step(t)
-    ptsg.pt_sync(ctx)
-    n_or_launch, or_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_OVERRELAX)
-    n_hb_launch, hb_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_HEATBATH)
-    n_rs_launch, rs_ms = ptsg.pt_kernel_time(ctx, ptsg.PT_K_RESIDENT)
-    ptsg.pt_profile(ctx, False)
-
+    wall, su_per_step, kt = run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every,
+                                args.steps, args.warmup)
     ps_per_su = wall / (args.steps * su_per_step) * 1e12
-    C = R * len(temps[0])
-    if mapping != "resident":
+    n_chains = sum(R * len(t) for t in temps)
+
+    if not mixed and mapping != "resident":
         # HBM roofline of the overrelaxation half-sweep: per spin update the
         # method must read and write the spin (24 B) and read the couplings
         # of the site (108 B), which the C chains of a sample share
+        n_l, ms = kt["or"]
         bytes_per_su = 24.0 + 108.0 / C
-        or_su = args.steps * n_or * n_chains * N       # over all launches of the timed region
-        su_per_launch = or_su / max(1, n_or_launch)
-        avg_s = or_ms / max(1, n_or_launch) / 1e3
+        or_su = args.steps * n_or * n_chains * L ** 3
+        su_per_launch = or_su / max(1, n_l)
+        avg_s = ms / max(1, n_l) / 1e3
         achieved = bytes_per_su * su_per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": ("cl_half_sweep_kernel<overrelax>" if mapping == "chain"
                                            else "half_sweep_kernel<overrelax>"),
@@ -185,19 +207,22 @@ def main():
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": pmc_traffic(kernel_hash()),
                 "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
                 "bytes_per_su": round(bytes_per_su, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
-                "launches": n_or_launch}
-    else:
+                "launches": n_l}
+    elif not mixed:
         # the lattice stays in LDS for the whole step: bounded by FP32 vector
-        # arithmetic, 138 flops per overrelaxation update (54-term field,
-        # reflection, renormalisation); packed FP32 is not used
-        su_per_launch = su_per_step * args.steps / max(1, n_rs_launch)
-        avg_s = rs_ms / max(1, n_rs_launch) / 1e3
+        # arithmetic (packed FP32 is not used)
+        n_l, ms = kt["rs"]
+        su_per_launch = su_per_step * args.steps / max(1, n_l)
+        avg_s = ms / max(1, n_l) / 1e3
         achieved = FLOPS_PER_SU * su_per_launch / avg_s / 1e12
         roof = {"bound": "alu", "kernel": "resident_step_kernel", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": None, "flops_per_su": FLOPS_PER_SU, "avg_launch_ms": round(avg_s * 1e3, 4),
-                "launches": n_rs_launch}
-    roof["kernel_source_sha256"] = kernel_hash()
+                "launches": n_l}
+    else:
+        roof = None
+    if roof is not None:
+        roof["kernel_source_sha256"] = kernel_hash()
 
     result = {
         "metric": METRIC,
@@ -213,30 +238,42 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.preset}: L={L}, {len(Ls)} samples x {len(temps[0])} temperatures x "
-                        f"{R} replicas = {n_chains} chains, Gaussian 3x3 couplings; step = {n_hb} HB + "
-                        f"{n_or} OR sweeps + PT pass" + (f", measurement every {every} steps" if every else ""),
-            "L": L, "samples": len(Ls), "temperatures": len(temps[0]), "replicas": R,
-            "spin_updates_per_step": su_per_step,
-            "mapping": mapping + " lanes",
+            "workload": f"{args.preset}: L={sorted(set(Ls))}, {len(Ls)} samples, {n_chains} chains, "
+                        f"Gaussian 3x3 couplings; step = {n_hb} HB + {n_or} OR sweeps + PT pass"
+                        + (f", measurement every {every} steps" if every else ""),
+            "L": L if not mixed else sorted(set(Ls)), "samples": len(Ls),
+            "temperatures": len(temps[0]) if not mixed else sorted({len(t) for t in temps}),
+            "replicas": R, "spin_updates_per_step": su_per_step,
+            "mapping": mapping + " lanes" if not mixed else "automatic per L",
             "graphs": not args.no_graphs,
         },
         "roofline": roof,
-        "heatbath_avg_launch_ms": round(hb_ms / max(1, n_hb_launch), 4),
     }
+    if kt is not None and kt["hb"][0]:
+        result["heatbath_avg_launch_ms"] = round(kt["hb"][1] / kt["hb"][0], 4)
+
+    if mixed:
+        # each L alone in its own context (per-lattice launches) beside the mixed batch
+        per_L = {}
+        for Lv in sorted(set(Ls)):
+            idx = [i for i, x in enumerate(Ls) if x == Lv]
+            w, su, _ = run(ptsg, torch, [Lv] * len(idx), [cpl[i] for i in idx], [temps[i] for i in idx],
+                           R, seed, flags, n_hb, n_or, 0, max(2, args.steps), 1, timing=False)
+            per_L[str(Lv)] = {"ps_per_su": round(w / (max(2, args.steps) * su) * 1e12, 3),
+                              "mapping": auto_mapping(Lv, R * len(temps[idx[0]])) + " lanes"}
+        result["per_L_separate_contexts"] = per_L
+    elif not args.no_plain:
+        pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS)
+        w, su, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
+                       timing=False)
+        plain = w / su * 1e12
+        result["plain_single_chain"] = {"value": round(plain, 3), "unit": "ps/SU",
+                                        "speedup_of_value": round(plain / ps_per_su, 3),
+                                        "form": "site lanes, one chain per workgroup (couplings "
+                                                "re-read by every chain), same step"}
     if not args.no_cpu_baseline:
-        per_hb, per_or, per_e, spent = cpu_baseline(L, cpl[0], temps[0], seed)
-        step_s = (n_hb * per_hb + n_or * per_or) * N + per_e
-        result["cpu_baseline"] = {
-            "value": round(step_s / ((n_hb + n_or) * N) * 1e12, 1),
-            "unit": "ps/SU",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"64 chains of sample 0 at L={L}: 1 heat-bath + 12 overrelaxation sweeps and one "
-                      f"energy each ({spent:.1f} s), composed to the {n_hb} HB + {n_or} OR step",
-        }
+        result["cpu_baseline"] = cpu_baseline(L, cpl[0], temps[0], seed, n_hb, n_or)
     print(json.dumps(result), flush=True)
-    ptsg.pt_free(ctx)
 
 
 if __name__ == "__main__":

@@ -132,7 +132,10 @@ enum {
      * first time each (n_hb, n_or) is used and replay it afterwards (the
      * Philox counters live in device memory, so replays are exact).  Steps
      * taken while kernel timing is enabled run without the graph. */
-    PT_F_GRAPHS = 8u
+    PT_F_GRAPHS = 8u,
+    /* The plain single-chain form, kept as a reference point: site lanes with
+     * one chain per workgroup, so every chain re-reads its couplings. */
+    PT_F_PLAIN = 16u
 };
 
 /* One sample (the single-lattice form of the API).  Equivalent to

@@ -111,7 +111,7 @@ int choose_split(int L, int batch)
 int choose_mapping(const pt_batch_desc *d, int s)
 {
     const int L = d->L[s], C = d->n_replicas * d->n_temps[s];
-    if (d->flags & PT_F_SITE_LANES) return kSiteLanes;
+    if (d->flags & (PT_F_SITE_LANES | PT_F_PLAIN)) return kSiteLanes;
     if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
     if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
     if (L <= kRsMaxL) return kResident;
@@ -693,7 +693,7 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
                 k.blocks = 1;
             } else if (k.mapping == kSiteLanes) {
                 k.blocks = (H + kSweepBlock - 1) / kSweepBlock;
-                k.G = choose_group(H, k.C, static_cast<int>(g.second.size()));
+                k.G = (d->flags & PT_F_PLAIN) ? 1 : choose_group(H, k.C, static_cast<int>(g.second.size()));
             } else {
                 for (int s : g.second)
                     for (int grp = 0; grp < (k.C + 63) / 64; ++grp) {
