@@ -94,17 +94,12 @@ def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
     }
 
 
-def auto_mapping(L, C):
-    if L <= 16:
-        return "resident"
-    waves = (C + 63) // 64
-    return "chain" if L <= 128 and 10 * C >= 9 * 64 * waves else "site"
-
-
 def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, warmup, timing=True):
     """Time `steps` steps after `warmup`; optionally a second pass with
     kernel-stamped events for the kernel durations."""
     ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
+    names = {ptsg.PT_F_SITE_LANES: "site", ptsg.PT_F_CHAIN_LANES: "chain", ptsg.PT_F_RESIDENT: "resident"}
+    maps = [names[ptsg.pt_get_mapping(ctx, s)] for s in range(len(Ls))]
     su_per_step = sum((n_hb + n_or) * R * len(t) * L ** 3 for L, t in zip(Ls, temps))
 
     def step(t):
@@ -138,7 +133,7 @@ def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, w
     ptsg.pt_free(ctx)
     del ctx
     torch.cuda.empty_cache()
-    return wall, su_per_step, kt
+    return wall, su_per_step, kt, maps
 
 
 def main():
@@ -151,9 +146,10 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain single-chain reference")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel of a step instead of replaying a captured hipGraph")
-    ap.add_argument("--mapping", choices=("auto", "site", "chain", "resident"), default="auto",
+    ap.add_argument("--mapping", choices=("auto", "tuned", "site", "chain", "resident"), default="auto",
                     help="sweep kernel mapping (auto: resident for L <= 16, else chain lanes when "
-                         "a sample's chains fill 64-lane waves to >= 90%%)")
+                         "a sample's chains fill 64-lane waves to >= 90%%; tuned: timed per L "
+                         "when the context is made)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path does not "
@@ -172,13 +168,12 @@ def main():
     # a mixed batch shares one step: 1 HB + 16 OR + PT
     n_or = 16 if p["n_or"] is None and mixed else (Ls[0] if p["n_or"] is None else p["n_or"])
     every = p["measure_every"]
-    flags = {"auto": 0, "site": ptsg.PT_F_SITE_LANES, "chain": ptsg.PT_F_CHAIN_LANES,
-             "resident": ptsg.PT_F_RESIDENT}[args.mapping]
+    flags = {"auto": 0, "tuned": ptsg.PT_F_AUTOTUNE, "site": ptsg.PT_F_SITE_LANES,
+             "chain": ptsg.PT_F_CHAIN_LANES, "resident": ptsg.PT_F_RESIDENT}[args.mapping]
     if not args.no_graphs:
         flags |= ptsg.PT_F_GRAPHS
     L = Ls[0]
     C = R * len(temps[0])
-    mapping = args.mapping if args.mapping != "auto" else auto_mapping(L, C)
 
     # plain copy of a known size: calibrates the rocprofv3 byte counters
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -186,8 +181,9 @@ def main():
     b.copy_(a)
     del a, b
 
-    wall, su_per_step, kt = run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every,
-                                args.steps, args.warmup)
+    wall, su_per_step, kt, maps = run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every,
+                                      args.steps, args.warmup)
+    mapping = maps[0]
     ps_per_su = wall / (args.steps * su_per_step) * 1e12
     n_chains = sum(R * len(t) for t in temps)
 
@@ -244,7 +240,9 @@ def main():
             "L": L if not mixed else sorted(set(Ls)), "samples": len(Ls),
             "temperatures": len(temps[0]) if not mixed else sorted({len(t) for t in temps}),
             "replicas": R, "spin_updates_per_step": su_per_step,
-            "mapping": mapping + " lanes" if not mixed else "automatic per L",
+            "mapping": (mapping + " lanes" if not mixed else
+                        {str(Lv): maps[Ls.index(Lv)] + " lanes" for Lv in sorted(set(Ls))}),
+            "mapping_choice": args.mapping,
             "graphs": not args.no_graphs,
         },
         "roofline": roof,
@@ -257,15 +255,16 @@ def main():
         per_L = {}
         for Lv in sorted(set(Ls)):
             idx = [i for i, x in enumerate(Ls) if x == Lv]
-            w, su, _ = run(ptsg, torch, [Lv] * len(idx), [cpl[i] for i in idx], [temps[i] for i in idx],
-                           R, seed, flags, n_hb, n_or, 0, max(2, args.steps), 1, timing=False)
+            w, su, _, m = run(ptsg, torch, [Lv] * len(idx), [cpl[i] for i in idx],
+                              [temps[i] for i in idx], R, seed, flags, n_hb, n_or, 0,
+                              max(2, args.steps), 1, timing=False)
             per_L[str(Lv)] = {"ps_per_su": round(w / (max(2, args.steps) * su) * 1e12, 3),
-                              "mapping": auto_mapping(Lv, R * len(temps[idx[0]])) + " lanes"}
+                              "mapping": m[0] + " lanes"}
         result["per_L_separate_contexts"] = per_L
     elif not args.no_plain:
         pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS)
-        w, su, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
-                       timing=False)
+        w, su, _, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
+                          timing=False)
         plain = w / su * 1e12
         result["plain_single_chain"] = {"value": round(plain, 3), "unit": "ps/SU",
                                         "speedup_of_value": round(plain / ps_per_su, 3),

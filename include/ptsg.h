@@ -135,8 +135,19 @@ enum {
     PT_F_GRAPHS = 8u,
     /* The plain single-chain form, kept as a reference point: site lanes with
      * one chain per workgroup, so every chain re-reads its couplings. */
-    PT_F_PLAIN = 16u
+    PT_F_PLAIN = 16u,
+    /* Autotuner: for each distinct (L, n_temps) in the batch, time one
+     * overrelaxation sweep of every applicable mapping on a temporary context
+     * (up to four of those samples) and use the fastest; results are cached
+     * for the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
+     * Runs kernels on the current device, so pt_workspace_size needs the
+     * device too when this flag is set. */
+    PT_F_AUTOTUNE = 32u
 };
+
+/* The mapping used for a sample: PT_F_SITE_LANES, PT_F_CHAIN_LANES or
+ * PT_F_RESIDENT. */
+pt_status pt_get_mapping(pt_ctx *ctx, int sample, unsigned *flag);
 
 /* One sample (the single-lattice form of the API).  Equivalent to
  * pt_init_batch with n_samples = 1, the null stream and library-owned

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <string>
@@ -144,7 +145,8 @@ std::string validate(const pt_batch_desc *d)
     return "";
 }
 
-Plan make_plan(const pt_batch_desc *d)
+// `forced`, when given, holds one mapping per sample (from the autotuner).
+Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
 {
     Plan p;
     p.S = d->n_samples;
@@ -156,7 +158,7 @@ Plan make_plan(const pt_batch_desc *d)
         const int L = d->L[s], T = d->n_temps[s];
         const int64_t N = static_cast<int64_t>(L) * L * L;
         const int C = p.R * T;
-        const int mapping = choose_mapping(d, s);
+        const int mapping = forced ? (*forced)[s] : choose_mapping(d, s);
         const int lanes = mapping == kChainLanes ? 64 : 1;
         const int C_alloc = (C + lanes - 1) / lanes * lanes;
         p.L.push_back(L);
@@ -515,15 +517,44 @@ extern "C" {
 
 const char *pt_last_error(void) { return g_err.c_str(); }
 
+static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vector<int> *forced);
+static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &mapping);
+
+// The autotuner runs only when no mapping is forced by a flag.
+static bool wants_autotune(const pt_batch_desc *d)
+{
+    const unsigned forced = PT_F_SITE_LANES | PT_F_CHAIN_LANES | PT_F_RESIDENT | PT_F_PLAIN;
+    return (d->flags & PT_F_AUTOTUNE) && !(d->flags & forced);
+}
+
 size_t pt_workspace_size(const pt_batch_desc *desc)
 {
     if (!validate(desc).empty()) return 0;
+    if (wants_autotune(desc)) {
+        std::vector<int> mapping;
+        if (autotuned_mappings(desc, mapping) != PT_OK) return 0;
+        return make_plan(desc, &mapping).bytes;
+    }
     return make_plan(desc).bytes;
 }
 
 pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
 {
     if (!out) return fail(PT_EINVAL, "ctx output pointer is NULL");
+    *out = nullptr;
+    const std::string why = validate(d);
+    if (!why.empty()) return fail(PT_EINVAL, why);
+    if (wants_autotune(d)) {
+        std::vector<int> mapping;
+        pt_status st = autotuned_mappings(d, mapping);
+        if (st != PT_OK) return st;
+        return init_batch(out, d, &mapping);
+    }
+    return init_batch(out, d, nullptr);
+}
+
+static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vector<int> *forced)
+{
     *out = nullptr;
     const std::string why = validate(d);
     if (!why.empty()) return fail(PT_EINVAL, why);
@@ -543,7 +574,7 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     if (hipGetDevice(&c->device) != hipSuccess) return fail(PT_EDEVICE, "no HIP device");
     c->stream = static_cast<hipStream_t>(d->stream);
     c->seed = d->seed;
-    c->plan = make_plan(d);
+    c->plan = make_plan(d, forced);
     Plan &P = c->plan;
     if (d->workspace) {
         if (d->workspace_bytes < P.bytes)
@@ -724,6 +755,99 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     PT_HIP(hipStreamSynchronize(st));
     *out = c;
     c = nullptr;  // disarm the guard
+    return PT_OK;
+}
+
+// Autotuner: for each distinct (L, n_temps) of the batch, time two
+// overrelaxation sweeps of every applicable mapping on a temporary context
+// holding up to four of those samples (best of three, after a warm-up), and
+// keep the fastest.  Results are cached per (device, L, n_temps, n_replicas,
+// samples timed, graphs) for the process.
+static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &mapping)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, bool>, int> cache;
+    const unsigned graphs = d->flags & PT_F_GRAPHS;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PT_EDEVICE, "no HIP device");
+    mapping.assign(d->n_samples, kSiteLanes);
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (int s = 0; s < d->n_samples; ++s) classes[{d->L[s], d->n_temps[s]}].push_back(s);
+    for (auto &cl : classes) {
+        const int L = cl.first.first;
+        const int n = std::min<int>(4, static_cast<int>(cl.second.size()));
+        const auto key = std::make_tuple(dev, L, cl.first.second, d->n_replicas, n, graphs != 0);
+        int best = L > 128 ? kSiteLanes : -1;  // the only mapping beyond L = 128
+        {
+            std::lock_guard<std::mutex> lock(mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) best = it->second;
+        }
+        if (best < 0) {
+            std::vector<int> Ls(n, L), Ts(n, cl.first.second);
+            std::vector<const double *> temps;
+            std::vector<const float *> cpl;
+            for (int q = 0; q < n; ++q) {
+                temps.push_back(d->temps[cl.second[q]]);
+                cpl.push_back(d->couplings[cl.second[q]]);
+            }
+            std::vector<std::pair<int, unsigned>> cands = {{kSiteLanes, PT_F_SITE_LANES}};
+            if (L <= 128) cands.push_back({kChainLanes, PT_F_CHAIN_LANES});
+            if (L <= kRsMaxL) cands.push_back({kResident, PT_F_RESIDENT});
+            double best_t = 0.0;
+            for (auto &cand : cands) {
+                pt_batch_desc t{};
+                t.n_samples = n;
+                t.L = Ls.data();
+                t.n_temps = Ts.data();
+                t.temps = temps.data();
+                t.couplings = cpl.data();
+                t.n_replicas = d->n_replicas;
+                t.seed = d->seed;
+                t.flags = cand.second | graphs;
+                pt_ctx *tc = nullptr;
+                pt_status st = init_batch(&tc, &t, nullptr);
+                if (st != PT_OK) return st;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                float ms = 0.0f, best_rep = 0.0f;
+                hipError_t he = hipEventCreate(&e0);
+                if (he == hipSuccess) he = hipEventCreate(&e1);
+                if (he == hipSuccess) st = pt_step(tc, 0, 2);
+                for (int rep = 0; rep < 3 && he == hipSuccess && st == PT_OK; ++rep) {
+                    he = hipEventRecord(e0, tc->stream);
+                    if (he == hipSuccess && (st = pt_step(tc, 0, 2)) == PT_OK) {
+                        he = hipEventRecord(e1, tc->stream);
+                        if (he == hipSuccess) he = hipEventSynchronize(e1);
+                        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                        if (he == hipSuccess && (rep == 0 || ms < best_rep)) best_rep = ms;
+                    }
+                }
+                ms = best_rep;
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+                pt_free(tc);
+                if (st != PT_OK) return st;
+                if (he != hipSuccess) return fail(PT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(he));
+                if (best < 0 || ms < best_t) {
+                    best = cand.first;
+                    best_t = ms;
+                }
+            }
+            std::lock_guard<std::mutex> lock(mu);
+            cache[key] = best;
+        }
+        for (int s : cl.second) mapping[s] = best;
+    }
+    return PT_OK;
+}
+
+pt_status pt_get_mapping(pt_ctx *c, int sample, unsigned *flag)
+{
+    if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
+    if (sample < 0 || sample >= c->plan.S) return fail(PT_EINVAL, "sample out of range");
+    if (!flag) return fail(PT_EINVAL, "output is NULL");
+    const int m = c->plan.mapping[sample];
+    *flag = m == kResident ? PT_F_RESIDENT : m == kChainLanes ? PT_F_CHAIN_LANES : PT_F_SITE_LANES;
     return PT_OK;
 }
 

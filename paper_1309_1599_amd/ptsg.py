@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(_PKG, "libptsg.so")
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PT_M_OVERLAP, PT_M_CHIRAL, PT_M_SD, PT_M_ALL = 1, 2, 4, 7
 PT_K_OVERRELAX, PT_K_HEATBATH, PT_K_RESIDENT = 0, 1, 2
-PT_F_SITE_LANES, PT_F_CHAIN_LANES, PT_F_RESIDENT, PT_F_GRAPHS, PT_F_PLAIN = 1, 2, 4, 8, 16
+PT_F_SITE_LANES, PT_F_CHAIN_LANES, PT_F_RESIDENT, PT_F_GRAPHS, PT_F_PLAIN, PT_F_AUTOTUNE = \
+    1, 2, 4, 8, 16, 32
 
 # numpy view of the C struct pt_meas (744 bytes, no padding)
 MEAS_DTYPE = np.dtype([
@@ -31,8 +32,8 @@ assert MEAS_DTYPE.itemsize == 744
 # Every symbol the C ABI exports (include/ptsg.h).
 EXPORTS = ["pt_init", "pt_workspace_size", "pt_init_batch", "pt_step", "pt_swap", "pt_measure",
            "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_energy", "pt_get_counters",
-           "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_free",
-           "pt_last_error"]
+           "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping",
+           "pt_free", "pt_last_error"]
 
 
 class PtError(RuntimeError):
@@ -84,6 +85,7 @@ def load_library(path=LIB_PATH):
         "pt_sync": (i, [vp]),
         "pt_profile": (i, [vp, i]),
         "pt_kernel_time": (i, [vp, i, C.POINTER(u64), C.POINTER(C.c_double)]),
+        "pt_get_mapping": (i, [vp, i, C.POINTER(C.c_uint)]),
         "pt_free": (None, [vp]),
         "pt_last_error": (C.c_char_p, []),
     }
@@ -264,6 +266,13 @@ def pt_kernel_time(ctx, kind):
     n, ms = C.c_uint64(), C.c_double()
     _check(load_library().pt_kernel_time(ctx.ptr, int(kind), C.byref(n), C.byref(ms)))
     return n.value, ms.value
+
+
+def pt_get_mapping(ctx, sample):
+    """PT_F_SITE_LANES, PT_F_CHAIN_LANES or PT_F_RESIDENT for `sample`."""
+    f = C.c_uint()
+    _check(load_library().pt_get_mapping(ctx.ptr, int(sample), C.byref(f)))
+    return f.value
 
 
 def pt_free(ctx):

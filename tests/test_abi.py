@@ -107,3 +107,14 @@ def test_workspace_reflects_mapping(lib):
     small = [np.zeros((3, 512, 3, 3), np.float32)]
     assert (ptsg.pt_workspace_size([8], small, temps, R, flags=ptsg.PT_F_RESIDENT)
             == ptsg.pt_workspace_size([8], small, temps, R, flags=ptsg.PT_F_SITE_LANES))
+
+
+def test_autotune_ignored_when_mapping_forced(lib):
+    """A mapping flag or the plain form switches the autotuner off, so the
+    plan (and its size) is the forced one and no device is needed."""
+    L, T, R = 24, 35, 2
+    cpl = [np.zeros((3, L ** 3, 3, 3), np.float32)]
+    temps = [inputs.geometric_temps(0.5, 1.5, T)]
+    for f in (ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES, ptsg.PT_F_PLAIN):
+        assert (ptsg.pt_workspace_size([L], cpl, temps, R, flags=f | ptsg.PT_F_AUTOTUNE)
+                == ptsg.pt_workspace_size([L], cpl, temps, R, flags=f))

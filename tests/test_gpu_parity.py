@@ -310,3 +310,45 @@ def test_graph_replays_match_eager(L, T, R):
         np.testing.assert_array_equal(ptsg.pt_get_energy(eager)[0], ptsg.pt_get_energy(graph)[0])
     ptsg.pt_free(eager)
     ptsg.pt_free(graph)
+
+
+def test_autotune_picks_valid_mapping_and_matches_forced():
+    """The autotuner picks a mapping per (L, n_temps) class; whatever it
+    picks, the result equals that of the same mapping forced by its flag.
+    Samples of one class share the choice."""
+    Ls = [8, 20, 8]
+    T, R, seed = 33, 2, 910   # 66 chains per sample
+    temps = [inputs.geometric_temps(0.6, 1.6, T)] * 3
+    tuned, cpl = _ctx(Ls, temps, R, seed, flags=ptsg.PT_F_AUTOTUNE)
+    picks = [ptsg.pt_get_mapping(tuned, s) for s in range(3)]
+    assert picks[0] == picks[2]
+    valid = {ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES, ptsg.PT_F_RESIDENT}
+    assert set(picks) <= valid
+    assert picks[1] != ptsg.PT_F_RESIDENT  # L = 20 is beyond the resident mapping
+    for s, L in enumerate(Ls):
+        forced, _ = _ctx([L], [temps[s]], R, seed, cpl=[cpl[s]], flags=picks[s])
+        assert ptsg.pt_get_mapping(forced, 0) == picks[s]
+        ptsg.pt_free(forced)
+    ptsg.pt_step(tuned, 1, 2)
+    ptsg.pt_swap(tuned)
+    # the whole tuned batch against site lanes: mappings are bit-identical
+    site, _ = _ctx(Ls, temps, R, seed, cpl=cpl, flags=ptsg.PT_F_SITE_LANES)
+    ptsg.pt_step(site, 1, 2)
+    ptsg.pt_swap(site)
+    for s in range(3):
+        for r in range(R):
+            np.testing.assert_array_equal(ptsg.pt_get_perm(tuned, s, r), ptsg.pt_get_perm(site, s, r))
+            for k in (0, T - 1):
+                np.testing.assert_array_equal(ptsg.pt_get_spins(tuned, s, r, k),
+                                              ptsg.pt_get_spins(site, s, r, k))
+    ptsg.pt_free(tuned)
+    ptsg.pt_free(site)
+
+
+def test_default_mapping_reported():
+    ctx, _ = _ctx([8, 20], [[1.0, 2.0]] * 2, 1, 920)
+    assert ptsg.pt_get_mapping(ctx, 0) == ptsg.PT_F_RESIDENT
+    assert ptsg.pt_get_mapping(ctx, 1) == ptsg.PT_F_SITE_LANES  # 2 chains: waves far from full
+    with pytest.raises(ptsg.PtError):
+        ptsg.pt_get_mapping(ctx, 2)
+    ptsg.pt_free(ctx)

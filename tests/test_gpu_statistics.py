@@ -2,7 +2,7 @@
 sample (same couplings and temperatures) with independent random streams,
 and the equilibrium averages must agree within their errors.
 
-Workload: L = 8, 8 temperatures evenly spaced in [0.5, 2.0], 2 replicas;
+Workload: L = 8, 8 temperatures evenly spaced in [0.7, 2.0], 2 replicas;
 each step = 1 heat-bath + 8 overrelaxation sweeps + 1 tempering pass, the
 paper's Monte Carlo step (Sec. III); measurements after every step.
 Observables per temperature: energy per spin, <q^2>, <q^4> of the scalar
@@ -11,6 +11,14 @@ overlap q = tr Q(0), and the second-moment correlation length of Sec. II.B
 run is discarded; errors from 16 blocks.  Rule: every |z| < 4 and at most a
 quarter of the |z| above 2.  (Nothing in the paper fixes these values for
 Gaussian couplings; the pin is GPU-versus-oracle agreement.)
+
+Calibration, from the oracle alone: eight runs with independent seeds gave
+pairwise z-scores with an rms of 1.34 (the 16-block errors miss part of the
+autocorrelation), so the errors are scaled by ERR_SCALE = 1.5.  The lowest
+temperature is 0.7 because at 0.5 two of four oracle seeds stayed in a
+metastable state (q^2 near 0.07 against 0.53) for the whole run: that
+temperature is not equilibrated in 2000 steps and no parity can be read
+from it.
 """
 import numpy as np
 import pytest
@@ -21,6 +29,7 @@ from paper_1309_1599_amd import inputs, ptsg
 pytestmark = pytest.mark.gpu
 
 L, T, R, STEPS = 8, 8, 2, 2000
+T_MIN, ERR_SCALE = 0.7, 1.5
 N = L ** 3
 
 
@@ -70,7 +79,7 @@ def _stats(b):
 
 
 def test_long_run_statistics_match_oracle():
-    temps = inputs.linear_temps(0.5, 2.0, T)
+    temps = inputs.linear_temps(T_MIN, 2.0, T)
     cpl = inputs.gaussian_couplings(L, 130915991)
     # GPU run
     ctx = ptsg.pt_init_batch([L], [cpl], [temps], R, 1001)
@@ -91,7 +100,7 @@ def test_long_run_statistics_match_oracle():
     mo, eo = _stats(_blocks(_observables(orc)))
     zs = []
     for k in ("e", "q2", "q4", "xi"):
-        z = (mg[k] - mo[k]) / np.sqrt(eg[k] ** 2 + eo[k] ** 2 + 1e-300)
+        z = (mg[k] - mo[k]) / (ERR_SCALE * np.sqrt(eg[k] ** 2 + eo[k] ** 2) + 1e-300)
         zs.append(z)
         print(k, np.round(mg[k], 4), np.round(mo[k], 4), np.round(z, 2))
     zs = np.concatenate(zs)
