@@ -147,9 +147,9 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel of a step instead of replaying a captured hipGraph")
     ap.add_argument("--mapping", choices=("auto", "tuned", "site", "chain", "resident"), default="auto",
-                    help="sweep kernel mapping (auto: resident for L <= 16, else chain lanes when "
-                         "a sample's chains fill 64-lane waves to >= 90%%; tuned: timed per L "
-                         "when the context is made)")
+                    help="sweep kernel mapping (auto: resident for L <= 16, chain lanes for 24 <= L "
+                         "<= 66 when a sample's chains fill 64-lane waves to >= 90%%, else site "
+                         "lanes; tuned: timed per L when the context is made)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path does not "

@@ -120,8 +120,9 @@ typedef struct {
  *   back so that its working set stays in the 256 MB Infinity Cache;
  * resident: one workgroup per chain keeps the whole lattice in LDS for all
  *   sweeps of a step (L <= 16).
- * Automatic: resident for L <= 16, else chain lanes when L <= 128 and the
- * sample's chains fill its 64-lane waves to >= 90%, else site lanes.  A forced mapping that does not
+ * Automatic: resident for L <= 16; chain lanes for 24 <= L <= 66 (one group
+ * of 64 chains plus the couplings fits in 256 MB) when the sample's chains
+ * fill its 64-lane waves to >= 90%; else site lanes.  A forced mapping that does not
  * apply to a sample (resident with L > 16, chain lanes with L > 128) falls
  * back to site lanes for it. */
 enum {
@@ -136,9 +137,10 @@ enum {
     /* The plain single-chain form, kept as a reference point: site lanes with
      * one chain per workgroup, so every chain re-reads its couplings. */
     PT_F_PLAIN = 16u,
-    /* Autotuner: for each distinct (L, n_temps) in the batch, time one
-     * overrelaxation sweep of every applicable mapping on a temporary context
-     * (up to four of those samples) and use the fastest; results are cached
+    /* Autotuner: for each distinct (L, n_temps) in the batch, time a step of
+     * 1 heat-bath + min(L, 32) overrelaxation sweeps of every applicable
+     * mapping on a temporary context (up to four of those samples) and use
+     * the fastest; results are cached
      * for the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
      * Runs kernels on the current device, so pt_workspace_size needs the
      * device too when this flag is set. */

@@ -116,9 +116,15 @@ int choose_mapping(const pt_batch_desc *d, int s)
     if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
     if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
     if (L <= kRsMaxL) return kResident;
-    // chain lanes only when the 64-lane waves are (nearly) full
+    // Chain lanes only when the 64-lane waves are (nearly) full and one group
+    // (64 chains of spins plus the sample's couplings) fits in the 256 MB
+    // Infinity Cache, where the group-major sweep order keeps it between
+    // half-sweeps; measured crossovers: site lanes are faster at L = 20 and
+    // at L = 96 and 128, chain lanes from L = 24 to 64.
     const int waves = (C + 63) / 64;
-    return (L <= 128 && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
+    const int64_t N = static_cast<int64_t>(L) * L * L;
+    const bool fits = (64 * 12 + 108) * N <= (256ll << 20);
+    return (L >= 24 && fits && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
 }
 
 std::string validate(const pt_batch_desc *d)
@@ -758,10 +764,11 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     return PT_OK;
 }
 
-// Autotuner: for each distinct (L, n_temps) of the batch, time two
-// overrelaxation sweeps of every applicable mapping on a temporary context
-// holding up to four of those samples (best of three, after a warm-up), and
-// keep the fastest.  Results are cached per (device, L, n_temps, n_replicas,
+// Autotuner: for each distinct (L, n_temps) of the batch, time a step of one
+// heat-bath and min(L, 32) overrelaxation sweeps of every applicable mapping
+// on a temporary context holding up to four of those samples (best of two,
+// after a warm-up step), and keep the fastest.  The step is long enough for
+// the chain-lane order to pay for its first, cold pass through the cache.  Results are cached per (device, L, n_temps, n_replicas,
 // samples timed, graphs) for the process.
 static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &mapping)
 {
@@ -812,10 +819,11 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
                 float ms = 0.0f, best_rep = 0.0f;
                 hipError_t he = hipEventCreate(&e0);
                 if (he == hipSuccess) he = hipEventCreate(&e1);
-                if (he == hipSuccess) st = pt_step(tc, 0, 2);
-                for (int rep = 0; rep < 3 && he == hipSuccess && st == PT_OK; ++rep) {
+                const int n_or = std::min(L, 32);
+                if (he == hipSuccess) st = pt_step(tc, 1, n_or);
+                for (int rep = 0; rep < 2 && he == hipSuccess && st == PT_OK; ++rep) {
                     he = hipEventRecord(e0, tc->stream);
-                    if (he == hipSuccess && (st = pt_step(tc, 0, 2)) == PT_OK) {
+                    if (he == hipSuccess && (st = pt_step(tc, 1, n_or)) == PT_OK) {
                         he = hipEventRecord(e1, tc->stream);
                         if (he == hipSuccess) he = hipEventSynchronize(e1);
                         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);

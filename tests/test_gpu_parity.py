@@ -287,16 +287,17 @@ def test_error_paths():
         ptsg.pt_get_spins(ctx, 0, 0, 5)
 
 
-@pytest.mark.parametrize("L,T,R", [(8, 4, 2), (20, 32, 2), (20, 3, 2)])
-def test_graph_replays_match_eager(L, T, R):
+@pytest.mark.parametrize("L,T,R,mapping", [(8, 4, 2, "resident"), (20, 32, 2, "chain"), (20, 3, 2, "site")])
+def test_graph_replays_match_eager(L, T, R, mapping):
     """A captured step replayed several times (with host reads between the
-    replays) gives exactly the eager result: resident, chain-lane and
-    site-lane classes respectively."""
+    replays) gives exactly the eager result, for each mapping."""
     seed = 880 + L + T
     temps = [inputs.geometric_temps(0.7, 1.5, T)]
     cpl = [inputs.gaussian_couplings(L, seed)]
-    eager = ptsg.pt_init_batch([L], cpl, temps, R, seed)
-    graph = ptsg.pt_init_batch([L], cpl, temps, R, seed, flags=ptsg.PT_F_GRAPHS)
+    f = MAPPINGS[mapping]
+    eager = ptsg.pt_init_batch([L], cpl, temps, R, seed, flags=f)
+    graph = ptsg.pt_init_batch([L], cpl, temps, R, seed, flags=f | ptsg.PT_F_GRAPHS)
+    assert ptsg.pt_get_mapping(graph, 0) == f
     for step in range(4):
         for ctx in (eager, graph):
             ptsg.pt_step(ctx, 1, 3)
@@ -346,9 +347,15 @@ def test_autotune_picks_valid_mapping_and_matches_forced():
 
 
 def test_default_mapping_reported():
-    ctx, _ = _ctx([8, 20], [[1.0, 2.0]] * 2, 1, 920)
-    assert ptsg.pt_get_mapping(ctx, 0) == ptsg.PT_F_RESIDENT
-    assert ptsg.pt_get_mapping(ctx, 1) == ptsg.PT_F_SITE_LANES  # 2 chains: waves far from full
-    with pytest.raises(ptsg.PtError):
-        ptsg.pt_get_mapping(ctx, 2)
-    ptsg.pt_free(ctx)
+    """The automatic choice: resident up to L = 16; chain lanes for
+    24 <= L <= 66 with (nearly) full 64-lane waves; site lanes otherwise."""
+    t32 = inputs.geometric_temps(0.6, 1.6, 32)
+    cases = [([8, 24], [[1.0, 2.0]] * 2, [ptsg.PT_F_RESIDENT, ptsg.PT_F_SITE_LANES]),  # 2 chains
+             ([20, 24, 64, 96], [t32] * 4, [ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES,
+                                            ptsg.PT_F_CHAIN_LANES, ptsg.PT_F_SITE_LANES])]
+    for Ls, temps, want in cases:
+        ctx, _ = _ctx(Ls, temps, 2, 920, cpl=[np.zeros((3, L ** 3, 3, 3), np.float32) for L in Ls])
+        assert [ptsg.pt_get_mapping(ctx, s) for s in range(len(Ls))] == want
+        with pytest.raises(ptsg.PtError):
+            ptsg.pt_get_mapping(ctx, len(Ls))
+        ptsg.pt_free(ctx)
