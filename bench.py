@@ -31,7 +31,7 @@ KERNEL_SOURCES = ["paper_1309_1599_amd/csrc/sweep.hip", "paper_1309_1599_amd/csr
                   "paper_1309_1599_amd/csrc/sweep_rs.hip",
                   "paper_1309_1599_amd/csrc/spin_update.hpp", "paper_1309_1599_amd/csrc/kernels.hpp",
                   "paper_1309_1599_amd/csrc/philox.hpp"]
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "overrelax_half_sweep_L64x8_pmc.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "overrelax_half_sweep_{preset}_pmc.txt")
 
 
 def kernel_hash():
@@ -42,16 +42,18 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def pmc_traffic(expected_hash):
+def pmc_traffic(preset, mapping, expected_hash):
     """HBM bytes per overrelaxation launch from the committed rocprofv3 --pmc
-    summary, if it was taken on the current kernel source."""
+    summary of this preset, if it was taken on the current kernel source with
+    the same mapping."""
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(PMC_SUMMARY.format(preset=preset)).read()
     except OSError:
         return None
     m = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b or m.group(1) != expected_hash:
+    k = re.search(r"mapping:\s*(\w+)", text)
+    if not m or not b or not k or m.group(1) != expected_hash or k.group(1) != mapping:
         return None
     return float(b.group(1))
 
@@ -200,7 +202,7 @@ def main():
         roof = {"bound": "hbm", "kernel": ("cl_half_sweep_kernel<overrelax>" if mapping == "chain"
                                            else "half_sweep_kernel<overrelax>"),
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": pmc_traffic(kernel_hash()),
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": pmc_traffic(args.preset, mapping, kernel_hash()),
                 "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
                 "bytes_per_su": round(bytes_per_su, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
                 "launches": n_l}
