@@ -150,7 +150,7 @@ def main():
                     help="launch every kernel of a step instead of replaying a captured hipGraph")
     ap.add_argument("--mapping", choices=("auto", "tuned", "site", "chain", "resident"), default="auto",
                     help="sweep kernel mapping (auto: resident for L <= 16, chain lanes for 24 <= L "
-                         "<= 66 when a sample's chains fill 64-lane waves to >= 90%%, else site "
+                         "<= 64 when a sample's chains fill 64-lane waves to >= 90%%, else site "
                          "lanes; tuned: timed per L when the context is made)")
     args = ap.parse_args()
     if args.gpus != 1:

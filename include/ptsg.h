@@ -120,9 +120,9 @@ typedef struct {
  *   back so that its working set stays in the 256 MB Infinity Cache;
  * resident: one workgroup per chain keeps the whole lattice in LDS for all
  *   sweeps of a step (L <= 16).
- * Automatic: resident for L <= 16; chain lanes for 24 <= L <= 66 (one group
- * of 64 chains plus the couplings fits in 256 MB) when the sample's chains
- * fill its 64-lane waves to >= 90%; else site lanes.  A forced mapping that does not
+ * Automatic: resident for L <= 16; chain lanes for 24 <= L <= 64 (the
+ * measured range where they are faster) when the sample's chains fill its
+ * 64-lane waves to >= 90%; else site lanes.  A forced mapping that does not
  * apply to a sample (resident with L > 16, chain lanes with L > 128) falls
  * back to site lanes for it. */
 enum {

@@ -17,6 +17,9 @@
 //          (This is the site-lane layout, lanes = 1.  The chain-lane layout,
 //          lanes = 64, stores group g = j/64 of a sample as
 //          [colour][H][component][64], lane = j%64; see spin_index.)
+//          Chain-lane samples keep the same 54 numbers per site site-major,
+//          [colour 2][H][54]: one 216-byte block per site, which a wave
+//          reads with five back-to-back scalar loads.
 //  cpls    per sample, site-major canonical couplings [N][3][3][3]: the
 //          three forward bond matrices of site i are floats 27i .. 27i+26.
 //  chains  global chain id = chain_base[sample] + rep*T + j, j = start slot.
@@ -32,7 +35,6 @@ constexpr int kMaxGroup = 128;     // chains per sweep workgroup (upper bound)
 constexpr int kMeasBlock = 256;
 constexpr int kClWaves = 4;        // chain-lane mapping: waves per workgroup
 constexpr int kClBlock = 64 * kClWaves;
-constexpr int kClSites = 16;       // consecutive packed sites per wave
 constexpr int kRsMaxBlock = 1024;  // lattice-resident mapping: threads per workgroup (max)
 constexpr int kRsMaxL = 16;        // largest L whose chain (12 N bytes) is kept in LDS
 constexpr int kOverlapQ = 45;      // plane partials: Q(0), Q(kx), Q(ky) re/im, 9 each
@@ -73,10 +75,10 @@ struct SweepParams {
 // Chain-lane mapping (one wave = 64 chains of one sample at one site).
 struct ClParams {
     float *spins;
-    const float *cpls;           // site-major couplings [N][3][3][3] per sample
+    const float *cpl;            // per-site packed couplings [colour][H][54] per sample
     const int *items;            // [n_items][2]: (sample, chain group)
     const int64_t *spin_base;
-    const int64_t *cpls_base;
+    const int64_t *cpl_base;
     const int *chain_base;
     const int *slot_of;
     const float *beta_of;
@@ -84,6 +86,7 @@ struct ClParams {
     int e_stride;
     int L, H, C, T;
     int split;                   // waves per packed row (divides L/2)
+    int strip;                   // row order: strips of `strip` y-rows, z-major within a strip (0: y-major)
     int n_tiles, per;            // workgroups of rows per item; per XCD (grid = 8*per)
     int colour;
     const uint32_t *counters;    // device [0]: heat-bath sweeps done, [1]: PT passes done

@@ -48,6 +48,7 @@ struct LatticeClass {
     int L = 0, T = 0, C = 0, lanes = 1, mapping = kSiteLanes;
     int G = 1;                       // site lanes: chains per workgroup
     int split = 1;                   // chain lanes: waves per packed row
+    int strip = 0;                   // chain lanes: y-rows per strip of the row order
     int blocks = 0;                  // workgroups per (sample or item) and half-sweep
     int batch = 1;                   // chain lanes: items per launch (Infinity Cache budget)
     std::vector<int> samples;
@@ -89,24 +90,33 @@ int max_split(int L)
 int cl_batch(int L, int n_items)
 {
     const int64_t N = static_cast<int64_t>(L) * L * L;
-    const int64_t item = 64 * 3 * N * 4 + 27 * N * 4;
+    const int64_t item = 64 * 3 * N * 4 + 54 * N * 4;
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_items, kCacheBudget / item)));
 }
 
-// Segments per packed row.  Whole rows per wave measured fastest at L = 64
-// (the four waves of a workgroup then cover four adjacent rows and share
-// their y-neighbour rows in L1); rows are split only when a launch would
-// otherwise have fewer than 1024 workgroups.
+// Segments per packed row: the most segments that keep at least 8 sites per
+// wave (at L = 64 four segments of 8 sites measured 14% faster than whole
+// rows: twice the waves in flight to cover the memory latency), then more
+// while a launch would have fewer than 1024 workgroups.
 int choose_split(int L, int batch)
 {
     const int Lh = L / 2;
     int best = 1;
-    for (int s = 1; s <= 8; s *= 2) {
-        if (Lh % s || (s > 1 && Lh / s < 2)) continue;
-        best = s;
-        if (static_cast<int64_t>(cl_blocks(L, s)) * batch >= 1024) break;
-    }
+    for (int s = 2; s <= 8; s *= 2)
+        if (Lh % s == 0 && Lh / s >= 8) best = s;
+    while (static_cast<int64_t>(cl_blocks(L, best)) * batch < 1024 && best < 8 && Lh % (2 * best) == 0 &&
+           Lh / (2 * best) >= 2)
+        best *= 2;
     return best;
+}
+
+// Rows are visited in strips of this many y-rows (z-major inside a strip);
+// 16 measured best at L = 64, against 8, 32 and plain y-major order.
+int choose_strip(int L)
+{
+    for (int w : {16, 8, 4})
+        if (L % w == 0) return w;
+    return 0;
 }
 
 int choose_mapping(const pt_batch_desc *d, int s)
@@ -116,15 +126,14 @@ int choose_mapping(const pt_batch_desc *d, int s)
     if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
     if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
     if (L <= kRsMaxL) return kResident;
-    // Chain lanes only when the 64-lane waves are (nearly) full and one group
-    // (64 chains of spins plus the sample's couplings) fits in the 256 MB
-    // Infinity Cache, where the group-major sweep order keeps it between
-    // half-sweeps; measured crossovers: site lanes are faster at L = 20 and
-    // at L = 96 and 128, chain lanes from L = 24 to 64.
+    // Chain lanes only when the 64-lane waves are (nearly) full and L is in
+    // the measured range where they win: site lanes are faster at L = 20
+    // and at L = 96 and 128, chain lanes from L = 24 to 64 (up to there a
+    // group of 64 chains, 201 MB at L = 64, stays in the 256 MB Infinity
+    // Cache between the half-sweeps that the group-major order runs back to
+    // back).
     const int waves = (C + 63) / 64;
-    const int64_t N = static_cast<int64_t>(L) * L * L;
-    const bool fits = (64 * 12 + 108) * N <= (256ll << 20);
-    return (L >= 24 && fits && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
+    return (L >= 24 && L <= 64 && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
 }
 
 std::string validate(const pt_batch_desc *d)
@@ -177,15 +186,15 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
         p.twid_base.push_back(twid);
         p.spin_base.push_back(spins);
         p.cpls_base.push_back(cpls);
-        p.cpl6_base.push_back(lanes == 1 ? cpl6 : -1);  // site-lane and resident mappings
+        p.cpl6_base.push_back(cpl6);  // [colour][54][H] (lanes = 1) or [colour][H][54] (chain lanes)
         chains += C;
         perm += C;
         betas += T;
         twid += 2 * L;
         spins += static_cast<int64_t>(C_alloc) * 3 * N;
         cpls += 27 * N;
+        cpl6 += 54 * N;
         if (lanes == 1) {
-            cpl6 += 54 * N;
             max_blocks = std::max<int>(max_blocks, static_cast<int>((N / 2 + kSweepBlock - 1) / kSweepBlock));
         } else {
             max_blocks = std::max(max_blocks, cl_blocks(L, max_split(L)));
@@ -300,10 +309,10 @@ ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour,
 {
     ClParams p{};
     p.spins = c->spins;
-    p.cpls = c->cpls;
+    p.cpl = c->cpl6;
     p.items = k.d_items + 2 * first_item;
     p.spin_base = c->d_spin_base;
-    p.cpls_base = c->d_cpls_base;
+    p.cpl_base = c->d_cpl6_base;
     p.chain_base = c->d_chain_base;
     p.slot_of = c->slot_of;
     p.beta_of = c->beta_of;
@@ -314,6 +323,7 @@ ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour,
     p.C = k.C;
     p.T = k.T;
     p.split = k.split;
+    p.strip = k.strip;
     p.n_tiles = k.blocks;
     p.per = (k.blocks + 7) / 8;
     p.colour = colour;
@@ -510,6 +520,19 @@ void pack_couplings(int L, const float *M, float *out)
             }
 }
 
+// Per-site packed couplings for the chain-lane mapping: out[colour][H][54],
+// the same 54 numbers per site as pack_couplings, site by site.
+void pack_couplings_site(int L, const float *M, float *out)
+{
+    const int N = L * L * L, H = N / 2;
+    std::vector<float> soa(static_cast<size_t>(54) * N);
+    pack_couplings(L, M, soa.data());
+    for (int c = 0; c < 2; ++c)
+        for (int p = 0; p < H; ++p)
+            for (int q = 0; q < 54; ++q)
+                out[(static_cast<int64_t>(c) * H + p) * 54 + q] = soa[(static_cast<int64_t>(c) * 54 + q) * H + p];
+}
+
 pt_status check_ctx(pt_ctx *c)
 {
     if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
@@ -698,12 +721,13 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                     std::memcpy(&buf[(i * 3 + mu) * 9], d->couplings[s] + (mu * N + i) * 9, 9 * sizeof(float));
             PT_HIP(hipMemcpy(c->cpls + P.cpls_base[s], buf.data(), buf.size() * sizeof(float),
                              hipMemcpyHostToDevice));
-            if (P.lanes[s] == 1) {
-                buf.assign(static_cast<size_t>(54 * N), 0.0f);
+            buf.assign(static_cast<size_t>(54 * N), 0.0f);
+            if (P.lanes[s] == 1)
                 pack_couplings(L, d->couplings[s], buf.data());
-                PT_HIP(hipMemcpy(c->cpl6 + P.cpl6_base[s], buf.data(), buf.size() * sizeof(float),
-                                 hipMemcpyHostToDevice));
-            }
+            else
+                pack_couplings_site(L, d->couplings[s], buf.data());
+            PT_HIP(hipMemcpy(c->cpl6 + P.cpl6_base[s], buf.data(), buf.size() * sizeof(float),
+                             hipMemcpyHostToDevice));
         }
     }
     // lattice classes (same L, T and mapping), swept by the same launches
@@ -740,6 +764,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                 const int n_items = static_cast<int>(k.items.size() / 2);
                 k.batch = cl_batch(k.L, n_items);
                 k.split = choose_split(k.L, k.batch);
+                k.strip = choose_strip(k.L);
                 k.blocks = cl_blocks(k.L, k.split);
                 k.d_items = ditems + 2 * at_items;
                 PT_HIP(hipMemcpy(k.d_items, k.items.data(), k.items.size() * sizeof(int),

@@ -2,10 +2,10 @@
 //
 // One wave = 64 chains of one sample at the same site: lane l owns chain
 // 64*g + l of chain group g.  All lanes read the same site, so
-//  * the site's bond matrices are wave-uniform: scalar loads bring them
-//    into SGPRs from the site-major couplings [N][3][3][3] (the forward bonds
-//    of a site are one contiguous 108-byte block), costing no vector
-//    registers;
+//  * the site's six matrices are wave-uniform: they sit in one 216-byte
+//    block of the per-site packed couplings [colour][H][54], which five
+//    scalar loads issued back to back bring into SGPRs (one memory round
+//    trip per site, no vector registers);
 //  * every spin access is a 256-byte row: the layout of a group is
 //    [colour][H][component][64 lanes], each lane uses the same vector offset
 //    (4*lane), the site enters through the scalar offset and the component
@@ -13,7 +13,10 @@
 //    addressing costs no vector ALU work.
 // Each wave walks a segment of one packed row of the active colour (fixed
 // y, z), so all its offsets advance by one site per step; the loads of the
-// next site are in flight while the current one is updated.
+// next site are in flight while the current one is updated.  Rows are
+// visited in strips of `strip` y-rows, z-major within a strip, so that the
+// y- and z-neighbour rows a wave reads were fetched into its XCD's L2 by
+// the waves of the rows just before it.
 // One chain group of an L = 64 sample is 201 MB and the sample's couplings
 // 28 MB: together they fit in the 256 MB Infinity Cache, which is why the
 // host runs all sweeps of one group back to back.
@@ -42,12 +45,19 @@ __device__ __forceinline__ void load_site(float (&v)[3], Rsrc r, unsigned voff, 
 }
 
 // Byte offsets (scalar) of the 7 sites a lane reads for one update, and the
-// float offsets of the bond matrices in the site-major couplings.
+// float offset of the site's block in the packed couplings.
 struct ClSite {
     unsigned own, nb[6];
-    unsigned fw, bw[3];  // forward block of the site; backward bond mu of site - e_mu
+    unsigned cpl;        // first of the site's 54 coupling floats
     int site;            // canonical index
 };
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+using CV16 = __attribute__((address_space(4))) const v16f;
+using CV4 = __attribute__((address_space(4))) const v4f;
+using CV2 = __attribute__((address_space(4))) const v2f;
 
 template <bool OWN>
 __device__ __forceinline__ void cl_gather(ClGather &g, Rsrc r, unsigned voff, const ClSite &t)
@@ -76,7 +86,7 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
     const unsigned voff = 4u * static_cast<unsigned>(lane);
     // The couplings are read-only for the whole launch: reading them through
     // the constant address space lets wave-uniform loads become scalar loads.
-    const CFloat *M = (const CFloat *)(P.cpls + P.cpls_base[s]);
+    const CFloat *M = (const CFloat *)(P.cpl + P.cpl_base[s]);
 
     uint32_t ctr3 = 0, hb_sweep = 0;
     float beta = 0.0f;
@@ -91,11 +101,17 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
     const int tile = xcd_tile(blockIdx.x, P.per);
     if (tile >= P.n_tiles) return;
     const int seg = tile * kClWaves + wave;
-    const int row = seg / P.split;
+    const int rl = seg / P.split;                 // row in visiting order
     const int len = Lh / P.split;
-    const int x0 = (seg - row * P.split) * len;
+    const int x0 = (seg - rl * P.split) * len;
+    int row = rl;                                 // packed row y + L*z
+    if (P.strip > 0) {
+        const int per_strip = L * P.strip;
+        const int q = rl % per_strip;
+        row = (q / P.strip) * L + (rl / per_strip) * P.strip + q % P.strip;
+    }
     double e_acc = 0.0;
-    if (row < L * L) {
+    if (rl < L * L) {  // strip order maps [0, L*L) onto itself
         const int y = row % L, z = row / L;
         const int par = (c + y + z) & 1;              // parity of x along this row
         const unsigned oth = static_cast<unsigned>(1 - c) * H;
@@ -105,16 +121,12 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
         const unsigned zp = static_cast<unsigned>((z == L - 1 ? row - (L - 1) * L : row + L) * Lh);
         const unsigned zm = static_cast<unsigned>((z == 0 ? row + (L - 1) * L : row - L) * Lh);
         const int rowc = L * row;                      // canonical index of (0, y, z)
-        const int rym = L * (y == 0 ? row + (L - 1) : row - 1);
-        const int rzm = L * (z == 0 ? row + (L - 1) * L : row - L);
-        // per-row bases; a site adds xh * kRow (spins) or x * 27 (couplings)
+        // per-row bases; a site adds xh * kRow (spins) or xh * 54 (couplings)
         const unsigned b_own = (static_cast<unsigned>(c) * H + rowp) * kRow;
         const unsigned b_x = (oth + rowp) * kRow;
         const unsigned b_yp = (oth + yp) * kRow, b_ym = (oth + ym) * kRow;
         const unsigned b_zp = (oth + zp) * kRow, b_zm = (oth + zm) * kRow;
-        const unsigned c_fw = static_cast<unsigned>(rowc) * 27u;
-        const unsigned c_by = static_cast<unsigned>(rym) * 27u + 9u;
-        const unsigned c_bz = static_cast<unsigned>(rzm) * 27u + 18u;
+        const unsigned c_row = (static_cast<unsigned>(c) * H + rowp) * 54u;
 
         auto site_at = [&](int xh) {
             ClSite t;
@@ -130,23 +142,25 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
             t.nb[4] = b_zp + o;
             t.nb[5] = b_zm + o;
             t.site = rowc + x;
-            const unsigned x27 = static_cast<unsigned>(x) * 27u;
-            t.fw = c_fw + x27;
-            t.bw[0] = c_fw + (x == 0 ? static_cast<unsigned>(L - 1) * 27u : x27 - 27u);
-            t.bw[1] = c_by + x27;
-            t.bw[2] = c_bz + x27;
+            t.cpl = c_row + static_cast<unsigned>(xh) * 54u;
             return t;
         };
 
         auto process = [&](const ClGather &gt, const ClSite &t) {
-            // A_{2mu} = M_{mu,x} (forward), A_{2mu+1} = M_{mu,x-e_mu}^T (backward)
-            const CFloat *F = M + t.fw;
-            const CFloat *B0 = M + t.bw[0], *B1 = M + t.bw[1], *B2 = M + t.bw[2];
+            // The site's 54 coefficients in five scalar loads.  The empty asm
+            // needs all of them at once, so the loads are issued together and
+            // waited for once, instead of one round trip per load.
+            const CFloat *A = M + t.cpl;
+            const v16f a0 = *(CV16 *)(A);
+            const v16f a1 = *(CV16 *)(A + 16);
+            const v16f a2 = *(CV16 *)(A + 32);
+            const v4f a3 = *(CV4 *)(A + 48);
+            const v2f a4 = *(CV2 *)(A + 52);
+            asm volatile("" ::"s"(a0), "s"(a1), "s"(a2), "s"(a3), "s"(a4));
             float h[3];
             local_field(gt.n, [&](int n, int a, int b) {
-                const int mu = n >> 1;
-                const CFloat *Bm = mu == 0 ? B0 : (mu == 1 ? B1 : B2);
-                return (n & 1) ? Bm[b * 3 + a] : F[mu * 9 + a * 3 + b];
+                const int q = n * 9 + a * 3 + b;
+                return q < 16 ? a0[q] : q < 32 ? a1[q - 16] : q < 48 ? a2[q - 32] : q < 52 ? a3[q - 48] : a4[q - 52];
             }, h);
             float sx, sy, sz;
             if constexpr (KIND == kHeatbath) {

@@ -88,9 +88,9 @@ def test_null_context_is_state_error(lib):
 
 
 def test_workspace_reflects_mapping(lib):
-    """Chain lanes pad a sample's chains to whole 64-lane groups and drop the
-    packed six-matrix couplings; site lanes, the plain form and the resident
-    mapping keep them.  (Plan only: no device is touched.)"""
+    """Chain lanes pad a sample's chains to whole 64-lane groups; every
+    mapping keeps 54 packed coupling floats per site (in its own order).
+    (Plan only: no device is touched.)"""
     L, T, R = 24, 35, 2          # 70 chains -> 2 groups of 64 lanes
     N = L ** 3
     cpl = [np.zeros((3, N, 3, 3), np.float32)]
@@ -100,8 +100,7 @@ def test_workspace_reflects_mapping(lib):
     plain = ptsg.pt_workspace_size([L], cpl, temps, R, flags=ptsg.PT_F_PLAIN)
     assert site == plain
     spins_site, spins_chain = 4 * 3 * N * 70, 4 * 3 * N * 128
-    cpl6 = 4 * 54 * N
-    assert chain - site == pytest.approx(spins_chain - spins_site - cpl6, abs=1 << 20)
+    assert chain - site == pytest.approx(spins_chain - spins_site, abs=1 << 20)
     # resident needs L <= 16; otherwise the sample falls back to site lanes
     assert ptsg.pt_workspace_size([L], cpl, temps, R, flags=ptsg.PT_F_RESIDENT) == site
     small = [np.zeros((3, 512, 3, 3), np.float32)]

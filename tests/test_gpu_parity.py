@@ -348,7 +348,7 @@ def test_autotune_picks_valid_mapping_and_matches_forced():
 
 def test_default_mapping_reported():
     """The automatic choice: resident up to L = 16; chain lanes for
-    24 <= L <= 66 with (nearly) full 64-lane waves; site lanes otherwise."""
+    24 <= L <= 64 with (nearly) full 64-lane waves; site lanes otherwise."""
     t32 = inputs.geometric_temps(0.6, 1.6, 32)
     cases = [([8, 24], [[1.0, 2.0]] * 2, [ptsg.PT_F_RESIDENT, ptsg.PT_F_SITE_LANES]),  # 2 chains
              ([20, 24, 64, 96], [t32] * 4, [ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES,
