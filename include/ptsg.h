@@ -200,6 +200,22 @@ pt_status pt_get_energy(pt_ctx *ctx, double *out);
 /* Heat-bath sweeps and PT passes done so far (the Philox counters). */
 pt_status pt_get_counters(pt_ctx *ctx, uint64_t *hb_sweeps, uint64_t *pt_passes);
 
+/* Checkpoint and resume.  pt_save writes the whole Monte Carlo state of a
+ * context into blob[cap]: every chain's spins (host [N][3] FP32, chains in
+ * (sample, replica, start slot) order), the slot permutations, the chain
+ * energies and the two Philox counters, behind a header that records the
+ * batch shape (L, n_temps, inverse temperatures, n_replicas, seed) and a
+ * 64-bit FNV-1a hash of each sample's couplings.  With blob == NULL it only
+ * stores the size it needs in *n_bytes; a smaller cap is PT_EINVAL.
+ * pt_load restores such a blob into a context created from the same
+ * descriptor (the kernel mapping and the graph flag may differ); a blob of
+ * another shape, seed or coupling set, or a damaged one, is PT_EINVAL and
+ * leaves the context unchanged.  Continuing after pt_load gives the spins,
+ * permutations and energies the saved run would have given.  Both are
+ * synchronous. */
+pt_status pt_save(pt_ctx *ctx, void *blob, size_t cap, size_t *n_bytes);
+pt_status pt_load(pt_ctx *ctx, const void *blob, size_t n_bytes);
+
 /* Queue all further work on `stream` (hipStream_t, NULL = null stream). */
 pt_status pt_set_stream(pt_ctx *ctx, void *stream);
 

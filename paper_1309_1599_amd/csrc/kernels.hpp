@@ -143,6 +143,11 @@ struct MeasParams {
     int Lmax, n_records;
     unsigned what;
     void *out;                   // device pt_meas[n_records]
+    // Sample `stage_sample` (-1: none) is read from `stage`, a site-lane
+    // copy of its chains ([chain][colour][component][H]) instead of `spins`.
+    const float *stage;
+    int stage_sample;
+    int rec0;                    // first record of a launch (blockIdx.x is relative)
 };
 
 // Optional kernel timing: when `start` is set, the dispatch itself stamps the
@@ -179,6 +184,12 @@ hipError_t launch_init_spins(float *spins, int64_t spin_base, int lanes, int L, 
 int cl_blocks(int L, int split);
 hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, float *canon,
                            bool to_canon, hipStream_t st);
-hipError_t launch_measure(const MeasParams &p, hipStream_t st);
+// Plane kernels for records [rec0, rec0 + n) (lattices up to L), then, once
+// all records are done, the per-record finalisation.
+hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st);
+hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st);
+// Copy the chains of a chain-lane sample into the site-lane layout (the
+// measurement kernels then read each component plane coalesced).
+hipError_t launch_cl_to_sl(const float *spins, int64_t base, int H, int C, float *stage, hipStream_t st);
 
 }  // namespace ptsg

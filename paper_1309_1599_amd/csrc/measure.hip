@@ -79,8 +79,12 @@ __device__ __forceinline__ RecordChains record_chains(const MeasParams &P, int r
     const int ja = ra * T + perm[ra * T + k];
     const int jb = rb * T + perm[rb * T + k];
     RecordChains rc;
-    rc.a = Chain{P.spins, P.spin_base[s], P.lanes[s], ja, L, L / 2, H};
-    rc.b = Chain{P.spins, P.spin_base[s], P.lanes[s], jb, L, L / 2, H};
+    const bool staged = s == P.stage_sample;
+    const float *src = staged ? P.stage : P.spins;
+    const int64_t base = staged ? 0 : P.spin_base[s];
+    const int lanes = staged ? 1 : P.lanes[s];
+    rc.a = Chain{src, base, lanes, ja, L, L / 2, H};
+    rc.b = Chain{src, base, lanes, jb, L, L / 2, H};
     rc.s = s;
     rc.L = L;
     rc.cw = P.twid + P.twid_base[s];
@@ -90,7 +94,7 @@ __device__ __forceinline__ RecordChains record_chains(const MeasParams &P, int r
 
 __global__ __launch_bounds__(kMeasBlock) void overlap_plane_kernel(MeasParams P)
 {
-    const int rec = blockIdx.x, z = blockIdx.y;
+    const int rec = P.rec0 + blockIdx.x, z = blockIdx.y;
     const RecordChains rc = record_chains(P, rec);
     const int L = rc.L;
     if (z >= L) return;
@@ -167,7 +171,7 @@ __device__ __forceinline__ void field64(const Chain &c, const float *cpls, int x
 
 __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
 {
-    const int rec = blockIdx.x, z = blockIdx.y;
+    const int rec = P.rec0 + blockIdx.x, z = blockIdx.y;
     const RecordChains rc = record_chains(P, rec);
     const int L = rc.L;
     if (z >= L) return;
@@ -269,15 +273,55 @@ __global__ void finalize_kernel(MeasParams P)
 
 }  // namespace
 
-hipError_t launch_measure(const MeasParams &p, hipStream_t st)
+namespace {
+
+// 64 sites x 64 chains x 3 components per workgroup: rows of 64 chains are
+// read coalesced, transposed in LDS (row pitch 65: no bank conflicts either
+// way) and written as rows of 64 sites per (chain, component).
+__global__ __launch_bounds__(256) void cl_to_sl_kernel(const float *spins, int64_t base, int H, int C,
+                                                       float *stage)
 {
-    if (p.n_records == 0) return hipSuccess;
-    const dim3 grid(p.n_records, p.Lmax);
+    __shared__ float tile[3][64][65];
+    const int p0 = blockIdx.x * 64, c = blockIdx.y, g = blockIdx.z;
+    const int lane = threadIdx.x & 63;
+    const float *src = spins + base + (static_cast<int64_t>(g) * 2 + c) * H * 192;
+    for (int row = threadIdx.x >> 6; row < 192; row += 4) {
+        const int q = row / 3, k = row - 3 * q;
+        if (p0 + q < H) tile[k][lane][q] = src[(static_cast<int64_t>(p0 + q) * 3 + k) * 64 + lane];
+    }
+    __syncthreads();
+    for (int row = threadIdx.x >> 6; row < 192; row += 4) {
+        const int l = row / 3, k = row - 3 * l;
+        const int j = g * 64 + l;
+        if (j < C && p0 + lane < H)
+            stage[((static_cast<int64_t>(j) * 2 + c) * 3 + k) * H + p0 + lane] = tile[k][l][lane];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    const dim3 grid(n, L);
     if (p.what & PT_M_OVERLAP)
         hipLaunchKernelGGL(overlap_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
     if (p.what & (PT_M_CHIRAL | PT_M_SD))
         hipLaunchKernelGGL(chiral_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st)
+{
+    if (p.n_records == 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3((p.n_records + 63) / 64), dim3(64), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_cl_to_sl(const float *spins, int64_t base, int H, int C, float *stage, hipStream_t st)
+{
+    const dim3 grid((H + 63) / 64, 2, (C + 63) / 64);
+    hipLaunchKernelGGL(cl_to_sl_kernel, grid, dim3(256), 0, st, spins, base, H, C, stage);
     return hipGetLastError();
 }
 

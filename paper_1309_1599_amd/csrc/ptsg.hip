@@ -234,7 +234,13 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
     p.off_meas = take(sizeof(pt_meas) * std::max(1, p.n_records));
     p.off_classes = take(sizeof(int) * p.S);
     p.off_items = take(sizeof(int) * 2 * std::max(1, p.n_items));
-    p.off_stage = take(sizeof(float) * 3 * static_cast<size_t>(p.Lmax) * p.Lmax * p.Lmax);
+    // staging: one chain in canonical order, or all chains of the largest
+    // chain-lane sample in the site-lane layout (measurement)
+    size_t stage = 3 * static_cast<size_t>(p.Lmax) * p.Lmax * p.Lmax;
+    for (int s = 0; s < p.S; ++s)
+        if (p.lanes[s] != 1)
+            stage = std::max(stage, 3 * static_cast<size_t>(p.L[s]) * p.L[s] * p.L[s] * p.R * p.T[s]);
+    p.off_stage = take(sizeof(float) * stage);
     p.off_counters = take(2 * sizeof(uint32_t));
     p.bytes = o;
     return p;
@@ -250,6 +256,8 @@ struct pt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     uint64_t seed = 0, hb_sweeps = 0, pt_passes = 0;
+    std::vector<uint64_t> cpl_hash;   // per sample: FNV-1a of the couplings given at init
+    std::vector<double> betas_host;   // per sample, concatenated: 1/T of each slot
     Plan plan;
     std::vector<LatticeClass> classes;
     char *ws = nullptr;
@@ -533,6 +541,17 @@ void pack_couplings_site(int L, const float *M, float *out)
                 out[(static_cast<int64_t>(c) * H + p) * 54 + q] = soa[(static_cast<int64_t>(c) * 54 + q) * H + p];
 }
 
+uint64_t fnv1a(const void *data, size_t n)
+{
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
 pt_status check_ctx(pt_ctx *c)
 {
     if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
@@ -682,6 +701,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
         for (int s = 0; s < P.S; ++s) {
             const int T = P.T[s], L = P.L[s];
             for (int k = 0; k < T; ++k) betas.push_back(1.0 / d->temps[s][k]);
+            c->cpl_hash.push_back(fnv1a(d->couplings[s], sizeof(float) * 27 * static_cast<size_t>(L) * L * L));
             for (int r = 0; r < P.R; ++r)
                 for (int j = 0; j < T; ++j) {
                     perm.push_back(j);
@@ -701,6 +721,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                     }
         }
         PT_HIP(hipMemcpy(c->betas, betas.data(), betas.size() * sizeof(double), hipMemcpyHostToDevice));
+        c->betas_host = betas;
         PT_HIP(hipMemcpy(c->perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
         PT_HIP(hipMemcpy(c->slot_of, slot.data(), slot.size() * sizeof(int), hipMemcpyHostToDevice));
         PT_HIP(hipMemcpy(c->beta_of, beta_of.data(), beta_of.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -1010,7 +1031,41 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
     m.n_records = P.n_records;
     m.what = what;
     m.out = c->meas;
-    PT_HIP(launch_measure(m, c->stream));
+    m.stage = c->stage;
+    m.stage_sample = -1;
+    // Records are ordered by sample.  Runs of site-lane samples are measured
+    // in place; a chain-lane sample is first copied to the site-lane layout
+    // (its lanes interleave 64 chains, which the per-site record kernels
+    // would read one float per cache line).
+    {
+        int first = 0, run_start = 0, run_L = 0;
+        auto flush = [&](int end) -> hipError_t {
+            if (end <= run_start) return hipSuccess;
+            MeasParams q = m;
+            q.rec0 = run_start;
+            return launch_measure_records(q, end - run_start, run_L, c->stream);
+        };
+        for (int s = 0; s < P.S; ++s) {
+            const int n = P.T[s] * P.R * (P.R - 1) / 2;
+            if (P.lanes[s] != 1) {
+                PT_HIP(flush(first));
+                const int L = P.L[s];
+                PT_HIP(launch_cl_to_sl(c->spins, P.spin_base[s], L * L * L / 2, P.R * P.T[s], c->stage,
+                                       c->stream));
+                MeasParams q = m;
+                q.stage_sample = s;
+                q.rec0 = first;
+                PT_HIP(launch_measure_records(q, n, L, c->stream));
+                run_start = first + n;
+                run_L = 0;
+            } else {
+                run_L = std::max(run_L, P.L[s]);
+            }
+            first += n;
+        }
+        PT_HIP(flush(first));
+        PT_HIP(launch_measure_finalize(m, c->stream));
+    }
     PT_HIP(hipMemcpyAsync(out, c->meas, sizeof(pt_meas) * P.n_records, hipMemcpyDeviceToHost,
                           c->stream));
     PT_HIP(hipStreamSynchronize(c->stream));
@@ -1104,6 +1159,193 @@ pt_status pt_get_counters(pt_ctx *c, uint64_t *hb, uint64_t *pt)
     if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
     if (hb) *hb = c->hb_sweeps;
     if (pt) *pt = c->pt_passes;
+    return PT_OK;
+}
+
+// Checkpoint blob: header, then per sample its shape and state.
+//   "PTSGCKP1" | u32 version=1 | u32 S | u32 R | u32 0 | u64 seed | u64 hb | u64 pt
+//   per sample: i32 L | i32 T | u64 coupling hash | f64 beta[T]
+//   per sample: i32 perm[R][T] | f64 E[R*T] | f32 spins[R*T][N][3] (chain order)
+//   u64 FNV-1a of everything before it
+extern "C++" {
+namespace {
+
+constexpr char kCkpMagic[8] = {'P', 'T', 'S', 'G', 'C', 'K', 'P', '1'};
+
+size_t checkpoint_bytes(const Plan &P)
+{
+    size_t n = 8 + 4 * 4 + 3 * 8;
+    for (int s = 0; s < P.S; ++s) {
+        const size_t T = P.T[s], C = static_cast<size_t>(P.R) * T;
+        const size_t N = static_cast<size_t>(P.L[s]) * P.L[s] * P.L[s];
+        n += 4 + 4 + 8 + 8 * T;
+        n += 4 * C + 8 * C + 4 * 3 * N * C;
+    }
+    return n + 8;
+}
+
+struct Writer {
+    unsigned char *p;
+    template <class V> void put(const V &v) { std::memcpy(p, &v, sizeof(V)); p += sizeof(V); }
+    void put(const void *src, size_t n) { std::memcpy(p, src, n); p += n; }
+};
+
+struct Reader {
+    const unsigned char *p, *end;
+    template <class V> bool get(V &v)
+    {
+        if (static_cast<size_t>(end - p) < sizeof(V)) return false;
+        std::memcpy(&v, p, sizeof(V));
+        p += sizeof(V);
+        return true;
+    }
+};
+
+}  // namespace
+}  // extern "C++"
+
+pt_status pt_save(pt_ctx *c, void *blob, size_t cap, size_t *n_bytes)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    const Plan &P = c->plan;
+    const size_t need = checkpoint_bytes(P);
+    if (n_bytes) *n_bytes = need;
+    if (!blob) return PT_OK;
+    if (cap < need) return fail(PT_EINVAL, "checkpoint buffer too small (" + std::to_string(need) + " bytes needed)");
+    PT_HIP(hipStreamSynchronize(c->stream));
+    Writer w{static_cast<unsigned char *>(blob)};
+    w.put(kCkpMagic, 8);
+    w.put(static_cast<uint32_t>(1));
+    w.put(static_cast<uint32_t>(P.S));
+    w.put(static_cast<uint32_t>(P.R));
+    w.put(static_cast<uint32_t>(0));
+    w.put(c->seed);
+    w.put(c->hb_sweeps);
+    w.put(c->pt_passes);
+    for (int s = 0; s < P.S; ++s) {
+        w.put(static_cast<int32_t>(P.L[s]));
+        w.put(static_cast<int32_t>(P.T[s]));
+        w.put(c->cpl_hash[s]);
+        w.put(c->betas_host.data() + P.beta_base[s], sizeof(double) * P.T[s]);
+    }
+    for (int s = 0; s < P.S; ++s) {
+        const int L = P.L[s], C = P.R * P.T[s];
+        const size_t n = 3 * static_cast<size_t>(L) * L * L;
+        PT_HIP(hipMemcpyAsync(w.p, c->perm + P.perm_base[s], sizeof(int) * C, hipMemcpyDeviceToHost, c->stream));
+        w.p += sizeof(int) * C;
+        PT_HIP(hipMemcpyAsync(w.p, c->E + P.chain_base[s], sizeof(double) * C, hipMemcpyDeviceToHost, c->stream));
+        w.p += sizeof(double) * C;
+        for (int j = 0; j < C; ++j) {
+            PT_HIP(launch_chain_io(c->spins, P.spin_base[s], P.lanes[s], L, j, c->stage, true, c->stream));
+            PT_HIP(hipMemcpyAsync(w.p, c->stage, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+            PT_HIP(hipStreamSynchronize(c->stream));
+            w.p += n * sizeof(float);
+        }
+    }
+    PT_HIP(hipStreamSynchronize(c->stream));
+    const size_t body = static_cast<size_t>(w.p - static_cast<unsigned char *>(blob));
+    w.put(fnv1a(blob, body));
+    return PT_OK;
+}
+
+pt_status pt_load(pt_ctx *c, const void *blob, size_t n_bytes)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!blob) return fail(PT_EINVAL, "checkpoint is NULL");
+    const Plan &P = c->plan;
+    const size_t need = checkpoint_bytes(P);
+    if (n_bytes != need)
+        return fail(PT_EINVAL, "checkpoint size " + std::to_string(n_bytes) + " does not match this context (" +
+                                   std::to_string(need) + " bytes)");
+    const unsigned char *b = static_cast<const unsigned char *>(blob);
+    uint64_t sum = 0;
+    std::memcpy(&sum, b + need - 8, 8);
+    if (sum != fnv1a(b, need - 8)) return fail(PT_EINVAL, "checkpoint checksum mismatch (damaged blob)");
+    Reader r{b, b + need - 8};
+    char magic[8];
+    for (char &ch : magic) r.get(ch);
+    uint32_t version = 0, S = 0, R = 0, pad = 0;
+    uint64_t seed = 0, hb = 0, pt = 0;
+    r.get(version);
+    r.get(S);
+    r.get(R);
+    r.get(pad);
+    r.get(seed);
+    r.get(hb);
+    r.get(pt);
+    if (std::memcmp(magic, kCkpMagic, 8) != 0 || version != 1) return fail(PT_EINVAL, "not a checkpoint of this library");
+    if (static_cast<int>(S) != P.S || static_cast<int>(R) != P.R)
+        return fail(PT_EINVAL, "checkpoint has another number of samples or replicas");
+    if (seed != c->seed) return fail(PT_EINVAL, "checkpoint was made with another seed");
+    for (int s = 0; s < P.S; ++s) {
+        int32_t L = 0, T = 0;
+        uint64_t h = 0;
+        r.get(L);
+        r.get(T);
+        r.get(h);
+        if (L != P.L[s] || T != P.T[s])
+            return fail(PT_EINVAL, "checkpoint sample " + std::to_string(s) + " has another L or n_temps");
+        if (h != c->cpl_hash[s])
+            return fail(PT_EINVAL, "checkpoint sample " + std::to_string(s) + " has other couplings");
+        for (int k = 0; k < T; ++k) {
+            double beta = 0.0;
+            r.get(beta);
+            if (beta != c->betas_host[P.beta_base[s] + k])
+                return fail(PT_EINVAL, "checkpoint sample " + std::to_string(s) + " has other temperatures");
+        }
+    }
+    {
+        // every permutation row must be a permutation of the slots
+        const unsigned char *q = r.p;
+        for (int s = 0; s < P.S; ++s) {
+            const int L = P.L[s], T = P.T[s], C = P.R * T;
+            std::vector<int> perm(C);
+            std::memcpy(perm.data(), q, sizeof(int) * C);
+            for (int rep = 0; rep < P.R; ++rep) {
+                std::vector<char> seen(T, 0);
+                for (int k = 0; k < T; ++k) {
+                    const int j = perm[rep * T + k];
+                    if (j < 0 || j >= T || seen[j]) return fail(PT_EINVAL, "checkpoint holds an invalid permutation");
+                    seen[j] = 1;
+                }
+            }
+            q += (sizeof(int) + sizeof(double)) * C + sizeof(float) * 3 * static_cast<size_t>(L) * L * L * C;
+        }
+    }
+    // validated: restore
+    PT_HIP(hipStreamSynchronize(c->stream));
+    std::vector<int> slot(P.n_chains);
+    std::vector<float> beta_of(P.n_chains);
+    for (int s = 0; s < P.S; ++s) {
+        const int L = P.L[s], T = P.T[s], C = P.R * T;
+        const size_t n = 3 * static_cast<size_t>(L) * L * L;
+        std::vector<int> perm(C);
+        std::memcpy(perm.data(), r.p, sizeof(int) * C);
+        r.p += sizeof(int) * C;
+        for (int rep = 0; rep < P.R; ++rep)
+            for (int k = 0; k < T; ++k) {
+                const int j = perm[rep * T + k];
+                slot[P.chain_base[s] + rep * T + j] = k;
+                beta_of[P.chain_base[s] + rep * T + j] = static_cast<float>(c->betas_host[P.beta_base[s] + k]);
+            }
+        PT_HIP(hipMemcpy(c->perm + P.perm_base[s], perm.data(), sizeof(int) * C, hipMemcpyHostToDevice));
+        PT_HIP(hipMemcpy(c->E + P.chain_base[s], r.p, sizeof(double) * C, hipMemcpyHostToDevice));
+        r.p += sizeof(double) * C;
+        for (int j = 0; j < C; ++j) {
+            PT_HIP(hipMemcpy(c->stage, r.p, n * sizeof(float), hipMemcpyHostToDevice));
+            PT_HIP(launch_chain_io(c->spins, P.spin_base[s], P.lanes[s], L, j, c->stage, false, c->stream));
+            PT_HIP(hipStreamSynchronize(c->stream));
+            r.p += n * sizeof(float);
+        }
+    }
+    PT_HIP(hipMemcpy(c->slot_of, slot.data(), sizeof(int) * slot.size(), hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(c->beta_of, beta_of.data(), sizeof(float) * beta_of.size(), hipMemcpyHostToDevice));
+    const uint32_t ctr[2] = {static_cast<uint32_t>(hb), static_cast<uint32_t>(pt)};
+    PT_HIP(hipMemcpy(c->counters, ctr, sizeof(ctr), hipMemcpyHostToDevice));
+    c->hb_sweeps = hb;
+    c->pt_passes = pt;
     return PT_OK;
 }
 

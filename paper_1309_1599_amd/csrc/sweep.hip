@@ -184,17 +184,21 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
     }
 }
 
-// E[chain] = -(sum of its partials), summed in block order.
-__global__ void energy_finalize_kernel(EnergyParams P)
+// E[chain] = -(sum of its partials): one wave per chain, lane l adds the
+// partials l, l+64, ... in order, then the lanes are combined by the fixed
+// shuffle tree of wave_sum (a fixed order: bit-reproducible).
+__global__ __launch_bounds__(256) void energy_finalize_kernel(EnergyParams P)
 {
     const int s = P.samples[blockIdx.y];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= P.C) return;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= P.C) return;   // wave-uniform
     const int chain = P.chain_base[s] + j;
     const double *e = P.e_part + static_cast<int64_t>(chain) * P.e_stride;
     double acc = 0.0;
-    for (int b = 0; b < P.n_blocks; ++b) acc += e[b];
-    P.E[chain] = -acc;
+    for (int b = lane; b < P.n_blocks; b += 64) acc += e[b];
+    acc = wave_sum(acc);
+    if (lane == 0) P.E[chain] = -acc;
 }
 
 // Hot start: z = 1 - 2u1 uniform on [-1,1], azimuth 2 pi u2 (uniform law on
@@ -283,8 +287,8 @@ hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_
 
 hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st)
 {
-    const dim3 grid((p.C + 63) / 64, n_samples);
-    hipLaunchKernelGGL(energy_finalize_kernel, grid, dim3(64), 0, st, p);
+    const dim3 grid((p.C + 3) / 4, n_samples);
+    hipLaunchKernelGGL(energy_finalize_kernel, grid, dim3(256), 0, st, p);
     return hipGetLastError();
 }
 

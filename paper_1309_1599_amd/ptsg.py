@@ -33,7 +33,7 @@ assert MEAS_DTYPE.itemsize == 744
 EXPORTS = ["pt_init", "pt_workspace_size", "pt_init_batch", "pt_step", "pt_swap", "pt_measure",
            "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_energy", "pt_get_counters",
            "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping",
-           "pt_free", "pt_last_error"]
+           "pt_save", "pt_load", "pt_free", "pt_last_error"]
 
 
 class PtError(RuntimeError):
@@ -86,6 +86,8 @@ def load_library(path=LIB_PATH):
         "pt_profile": (i, [vp, i]),
         "pt_kernel_time": (i, [vp, i, C.POINTER(u64), C.POINTER(C.c_double)]),
         "pt_get_mapping": (i, [vp, i, C.POINTER(C.c_uint)]),
+        "pt_save": (i, [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "pt_load": (i, [vp, vp, C.c_size_t]),
         "pt_free": (None, [vp]),
         "pt_last_error": (C.c_char_p, []),
     }
@@ -273,6 +275,24 @@ def pt_get_mapping(ctx, sample):
     f = C.c_uint()
     _check(load_library().pt_get_mapping(ctx.ptr, int(sample), C.byref(f)))
     return f.value
+
+
+def pt_save(ctx):
+    """The context's whole Monte Carlo state as a numpy uint8 array."""
+    lib = load_library()
+    n = C.c_size_t()
+    _check(lib.pt_save(ctx.ptr, None, 0, C.byref(n)))
+    blob = np.empty(n.value, np.uint8)
+    _check(lib.pt_save(ctx.ptr, blob.ctypes.data_as(C.c_void_p), blob.nbytes, C.byref(n)))
+    return blob
+
+
+def pt_load(ctx, blob):
+    """Restore a state saved by pt_save into a context made from the same
+    descriptor."""
+    blob = np.ascontiguousarray(np.frombuffer(blob, np.uint8) if isinstance(blob, (bytes, bytearray))
+                                else np.asarray(blob, np.uint8))
+    _check(load_library().pt_load(ctx.ptr, blob.ctypes.data_as(C.c_void_p), blob.nbytes))
 
 
 def pt_free(ctx):

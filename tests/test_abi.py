@@ -88,9 +88,10 @@ def test_null_context_is_state_error(lib):
 
 
 def test_workspace_reflects_mapping(lib):
-    """Chain lanes pad a sample's chains to whole 64-lane groups; every
-    mapping keeps 54 packed coupling floats per site (in its own order).
-    (Plan only: no device is touched.)"""
+    """Chain lanes pad a sample's chains to whole 64-lane groups and stage
+    all chains of the sample in the site-lane layout for measurements (other
+    mappings stage one chain); every mapping keeps 54 packed coupling floats
+    per site (in its own order).  (Plan only: no device is touched.)"""
     L, T, R = 24, 35, 2          # 70 chains -> 2 groups of 64 lanes
     N = L ** 3
     cpl = [np.zeros((3, N, 3, 3), np.float32)]
@@ -100,7 +101,8 @@ def test_workspace_reflects_mapping(lib):
     plain = ptsg.pt_workspace_size([L], cpl, temps, R, flags=ptsg.PT_F_PLAIN)
     assert site == plain
     spins_site, spins_chain = 4 * 3 * N * 70, 4 * 3 * N * 128
-    assert chain - site == pytest.approx(spins_chain - spins_site, abs=1 << 20)
+    stage_extra = 4 * 3 * N * (70 - 1)
+    assert chain - site == pytest.approx(spins_chain - spins_site + stage_extra, abs=1 << 20)
     # resident needs L <= 16; otherwise the sample falls back to site lanes
     assert ptsg.pt_workspace_size([L], cpl, temps, R, flags=ptsg.PT_F_RESIDENT) == site
     small = [np.zeros((3, 512, 3, 3), np.float32)]
@@ -117,3 +119,9 @@ def test_autotune_ignored_when_mapping_forced(lib):
     for f in (ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES, ptsg.PT_F_PLAIN):
         assert (ptsg.pt_workspace_size([L], cpl, temps, R, flags=f | ptsg.PT_F_AUTOTUNE)
                 == ptsg.pt_workspace_size([L], cpl, temps, R, flags=f))
+
+
+def test_checkpoint_calls_need_a_context(lib):
+    n = C.c_size_t()
+    assert lib.pt_save(None, None, 0, C.byref(n)) == ptsg.PT_ESTATE
+    assert lib.pt_load(None, None, 0) == ptsg.PT_ESTATE
