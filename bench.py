@@ -166,6 +166,10 @@ def main():
                     help="sweep kernel mapping (auto: resident for L <= 16, chain lanes for 24 <= L "
                          "<= 64 when a sample's chains fill 64-lane waves to >= 90%%, else site "
                          "lanes; tuned: timed per L when the context is made)")
+    ap.add_argument("--couplings", choices=("gaussian", "bimodal"), default="gaussian",
+                    help="gaussian: 9 iid N(0,1) entries per bond (the workload); bimodal: the paper's "
+                         "family J*1 + D_sym, J = +-1, D_ab = +-0.5, stored as one byte per bond "
+                         "(PT_F_BIMODAL) where the mapping allows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path does not "
@@ -179,6 +183,9 @@ def main():
     torch.cuda.set_device(0)
     p = inputs.PRESETS[args.preset]
     Ls, cpl, temps, R, seed = inputs.preset_inputs(args.preset)
+    bimodal = args.couplings == "bimodal"
+    if bimodal:
+        cpl = [inputs.bimodal_couplings(L, 0.5, seed, s) for s, L in enumerate(Ls)]
     n_hb = p["n_hb"]
     mixed = len(set(Ls)) > 1
     # a mixed batch shares one step: 1 HB + 16 OR + PT
@@ -188,6 +195,8 @@ def main():
              "chain": ptsg.PT_F_CHAIN_LANES, "resident": ptsg.PT_F_RESIDENT}[args.mapping]
     if not args.no_graphs:
         flags |= ptsg.PT_F_GRAPHS
+    if bimodal:
+        flags |= ptsg.PT_F_BIMODAL
     L = Ls[0]
     C = R * len(temps[0])
 
@@ -206,9 +215,10 @@ def main():
     if not mixed and mapping != "resident":
         # HBM roofline of the overrelaxation half-sweep: per spin update the
         # method must read and write the spin (24 B) and read the couplings
-        # of the site (108 B), which the C chains of a sample share
+        # of the site (108 B as floats, 3 B as bimodal codes), which the C
+        # chains of a sample share
         n_l, ms = kt["or"]
-        bytes_per_su = 24.0 + 108.0 / C
+        bytes_per_su = 24.0 + (3.0 if bimodal else 108.0) / C
         or_su = args.steps * n_or * n_chains * L ** 3
         su_per_launch = or_su / max(1, n_l)
         avg_s = ms / max(1, n_l) / 1e3
@@ -251,7 +261,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.preset}: L={sorted(set(Ls))}, {len(Ls)} samples, {n_chains} chains, "
-                        f"Gaussian 3x3 couplings; step = {n_hb} HB + {n_or} OR sweeps + PT pass"
+                        + ("bimodal couplings (D = 0.5, one byte per bond); step" if bimodal
+                           else "Gaussian 3x3 couplings; step") + f" = {n_hb} HB + {n_or} OR sweeps + PT pass"
                         + (f", measurement every {every} steps" if every else ""),
             "L": L if not mixed else sorted(set(Ls)), "samples": len(Ls),
             "temperatures": len(temps[0]) if not mixed else sorted({len(t) for t in temps}),
@@ -283,7 +294,7 @@ def main():
                               "mapping": m[0] + " lanes"}
         result["per_L_separate_contexts"] = per_L
     elif not args.no_plain:
-        pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS)
+        pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS) | (ptsg.PT_F_BIMODAL if bimodal else 0)
         w, su, _, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
                           timing=False)
         plain = w / su * 1e12

@@ -144,7 +144,15 @@ enum {
      * for the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
      * Runs kernels on the current device, so pt_workspace_size needs the
      * device too when this flag is set. */
-    PT_F_AUTOTUNE = 32u
+    PT_F_AUTOTUNE = 32u,
+    /* The paper's coupling family (Sec. II.A): every bond is
+     * M = J*1 + D_sym, J = +-1, the six entries D_ab (a <= b) of the
+     * symmetric D equal to +-D, one D > 0 per sample (checked bit for bit;
+     * PT_EINVAL otherwise).  Site-lane samples then keep one byte per bond
+     * (8 bytes per site instead of 216) and decode it in the sweep kernel;
+     * results are bit-identical to passing the same matrices without the
+     * flag.  Chain-lane and resident samples keep their float layouts. */
+    PT_F_BIMODAL = 64u
 };
 
 /* The mapping used for a sample: PT_F_SITE_LANES, PT_F_CHAIN_LANES or
@@ -157,7 +165,8 @@ pt_status pt_get_mapping(pt_ctx *ctx, int sample, unsigned *flag);
 pt_status pt_init(pt_ctx **ctx, int L, const float *couplings, const double *temps,
                   int n_temps, int n_replicas, uint64_t seed);
 
-/* Bytes of device workspace a batch needs (0 if the descriptor is invalid). */
+/* Bytes of device workspace a batch needs (0 if the descriptor is invalid;
+ * pt_last_error then says why). */
 size_t pt_workspace_size(const pt_batch_desc *desc);
 
 /* Create a context for a batch of samples (see pt_batch_desc). */

@@ -59,6 +59,8 @@ struct SweepParams {
     const int *samples;          // sample ids of this launch (one lattice class)
     const int64_t *spin_base;    // per sample: float offset of its chain 0
     const int64_t *cpl_base;     // per sample: float offset of its couplings
+    const float *bm_D;           // per sample: D of the bimodal family
+    int bimodal;                 // cpl holds 8 bytes of bond codes per site ([colour][H][8])
     const int *chain_base;       // per sample: global id of its chain 0
     const int *slot_of;          // per global chain: current temperature slot
     const float *beta_of;        // per global chain: 1/T of its slot

@@ -61,12 +61,14 @@ struct LatticeClass {
 struct Plan {
     int S = 0, R = 0, n_chains = 0, Lmax = 0, n_records = 0, e_stride = 1, twid_len = 0;
     std::vector<int> L, T, lanes, mapping, chain_base, perm_base, beta_base, twid_base;
+    std::vector<char> codes;          // per sample: bond codes instead of packed floats (PT_F_BIMODAL, site lanes)
     std::vector<int64_t> spin_base, cpls_base, cpl6_base;
     int64_t spin_floats = 0, cpls_floats = 0, cpl6_floats = 0;
     int total_perm = 0, n_items = 0;
     size_t off_spins = 0, off_cpls = 0, off_cpl6 = 0, off_slot = 0, off_beta_of = 0, off_E = 0,
            off_perm = 0, off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0,
            off_mpart = 0, off_meas = 0, off_classes = 0, off_items = 0, off_stage = 0, off_counters = 0,
+           off_bmD = 0,
            bytes = 0;
 };
 
@@ -136,6 +138,55 @@ int choose_mapping(const pt_batch_desc *d, int s)
     return (L >= 24 && L <= 64 && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
 }
 
+// The paper's coupling family (Sec. II.A): M = J*1 + D_sym with J = +-1 and
+// the six independent entries of the symmetric D equal to +-D.  A bond is
+// one byte: bit 0 set for J = -1, bits 1..6 set for a negative D entry, in
+// the order 00, 11, 22, 01, 02, 12.  Decoding computes the diagonal as the
+// FP32 sum J + d, exactly as the device decoder does.
+void bimodal_matrix(unsigned code, float D, float m[9])
+{
+    const float J = (code & 1u) ? -1.0f : 1.0f;
+    float d[6];
+    for (int k = 0; k < 6; ++k) d[k] = ((code >> (1 + k)) & 1u) ? -D : D;
+    m[0] = J + d[0];
+    m[4] = J + d[1];
+    m[8] = J + d[2];
+    m[1] = m[3] = d[3];
+    m[2] = m[6] = d[4];
+    m[5] = m[7] = d[5];
+}
+
+// The code of bond matrix m (row-major), or -1 if m is not J*1 + D_sym of
+// this D bit for bit.
+int bimodal_code(const float m[9], float D)
+{
+    for (unsigned jbit = 0; jbit < 2; ++jbit) {
+        const float J = jbit ? -1.0f : 1.0f;
+        unsigned c = jbit;
+        for (int a = 0; a < 3; ++a)
+            if (m[4 * a] == J + (-D)) c |= 1u << (1 + a);
+        if (m[1] == -D) c |= 1u << 4;
+        if (m[2] == -D) c |= 1u << 5;
+        if (m[5] == -D) c |= 1u << 6;
+        float t[9];
+        bimodal_matrix(c, D, t);
+        if (std::memcmp(t, m, sizeof(t)) == 0) return static_cast<int>(c);
+    }
+    return -1;
+}
+
+// D of a sample in the family (> 0, from its first bond), or 0 if the sample
+// is not in it.
+float bimodal_D(int L, const float *M)
+{
+    const float D = std::fabs(M[1]);
+    if (!(D > 0.0f) || !std::isfinite(D)) return 0.0f;
+    const int64_t nb = 3 * static_cast<int64_t>(L) * L * L;
+    for (int64_t b = 0; b < nb; ++b)
+        if (bimodal_code(M + 9 * b, D) < 0) return 0.0f;
+    return D;
+}
+
 std::string validate(const pt_batch_desc *d)
 {
     if (!d) return "descriptor is NULL";
@@ -156,6 +207,9 @@ std::string validate(const pt_batch_desc *d)
             if (k > 0 && !(t > d->temps[s][k - 1]))
                 return "sample " + std::to_string(s) + ": temperatures must be strictly ascending";
         }
+        if ((d->flags & PT_F_BIMODAL) && bimodal_D(L, d->couplings[s]) == 0.0f)
+            return "sample " + std::to_string(s) +
+                   ": PT_F_BIMODAL needs every bond to be J*1 + D_sym with J = +-1 and D_ab = +-D, D > 0";
     }
     return "";
 }
@@ -193,7 +247,9 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
         twid += 2 * L;
         spins += static_cast<int64_t>(C_alloc) * 3 * N;
         cpls += 27 * N;
-        cpl6 += 54 * N;
+        const bool codes = (d->flags & PT_F_BIMODAL) && mapping == kSiteLanes;
+        p.codes.push_back(codes);
+        cpl6 += codes ? 2 * N : 54 * N;   // 8 bytes per site, or 54 floats
         if (lanes == 1) {
             max_blocks = std::max<int>(max_blocks, static_cast<int>((N / 2 + kSweepBlock - 1) / kSweepBlock));
         } else {
@@ -242,6 +298,7 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
             stage = std::max(stage, 3 * static_cast<size_t>(p.L[s]) * p.L[s] * p.L[s] * p.R * p.T[s]);
     p.off_stage = take(sizeof(float) * stage);
     p.off_counters = take(2 * sizeof(uint32_t));
+    p.off_bmD = take(sizeof(float) * p.S);
     p.bytes = o;
     return p;
 }
@@ -269,6 +326,7 @@ struct pt_ctx {
     pt_meas *meas = nullptr;
     float *stage = nullptr;           // one chain in canonical [N][3] order
     uint32_t *counters = nullptr;     // device: heat-bath sweeps, PT passes
+    float *bm_D = nullptr;            // device, per sample: D of the bimodal family (PT_F_BIMODAL)
     bool use_graphs = false;
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
@@ -293,6 +351,8 @@ SweepParams sweep_params(pt_ctx *c, const LatticeClass &k, int colour, uint32_t 
     p.samples = k.d_samples;
     p.spin_base = c->d_spin_base;
     p.cpl_base = c->d_cpl6_base;
+    p.bm_D = c->bm_D;
+    p.bimodal = c->plan.codes[k.samples[0]];
     p.chain_base = c->d_chain_base;
     p.slot_of = c->slot_of;
     p.beta_of = c->beta_of;
@@ -552,6 +612,30 @@ uint64_t fnv1a(const void *data, size_t n)
     return h;
 }
 
+// Bond codes of a bimodal sample for the site-lane kernel: out[colour][H][8],
+// byte n of a site = code of its matrix A_n (n = 0..5: forward and backward
+// bond along x, y, z; the family is symmetric, so A_{2mu+1} = M_{mu,x-e_mu}
+// has the code of that bond), bytes 6 and 7 zero.
+void pack_bond_codes(int L, const float *M, float D, uint8_t *out)
+{
+    const int N = L * L * L, H = N / 2, Lh = L / 2;
+    for (int z = 0; z < L; ++z)
+        for (int y = 0; y < L; ++y)
+            for (int x = 0; x < L; ++x) {
+                const int i = x + L * (y + L * z);
+                const int col = (x + y + z) & 1;
+                const int p = (x >> 1) + Lh * (y + L * z);
+                const int back[3] = {((x + L - 1) % L) + L * (y + L * z), x + L * (((y + L - 1) % L) + L * z),
+                                     x + L * (y + L * ((z + L - 1) % L))};
+                uint8_t *o = out + (static_cast<int64_t>(col) * H + p) * 8;
+                for (int mu = 0; mu < 3; ++mu) {
+                    o[2 * mu] = static_cast<uint8_t>(bimodal_code(M + (static_cast<int64_t>(mu) * N + i) * 9, D));
+                    o[2 * mu + 1] =
+                        static_cast<uint8_t>(bimodal_code(M + (static_cast<int64_t>(mu) * N + back[mu]) * 9, D));
+                }
+            }
+}
+
 pt_status check_ctx(pt_ctx *c)
 {
     if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
@@ -577,7 +661,11 @@ static bool wants_autotune(const pt_batch_desc *d)
 
 size_t pt_workspace_size(const pt_batch_desc *desc)
 {
-    if (!validate(desc).empty()) return 0;
+    const std::string why = validate(desc);
+    if (!why.empty()) {
+        fail(PT_EINVAL, why);
+        return 0;
+    }
     if (wants_autotune(desc)) {
         std::vector<int> mapping;
         if (autotuned_mappings(desc, mapping) != PT_OK) return 0;
@@ -655,6 +743,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     c->meas = reinterpret_cast<pt_meas *>(w + P.off_meas);
     c->stage = reinterpret_cast<float *>(w + P.off_stage);
     c->counters = reinterpret_cast<uint32_t *>(w + P.off_counters);
+    c->bm_D = reinterpret_cast<float *>(w + P.off_bmD);
     c->use_graphs = (d->flags & PT_F_GRAPHS) != 0;
     {
         const uint32_t zero[2] = {0u, 0u};
@@ -742,6 +831,14 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                     std::memcpy(&buf[(i * 3 + mu) * 9], d->couplings[s] + (mu * N + i) * 9, 9 * sizeof(float));
             PT_HIP(hipMemcpy(c->cpls + P.cpls_base[s], buf.data(), buf.size() * sizeof(float),
                              hipMemcpyHostToDevice));
+            if (P.codes[s]) {
+                const float D = bimodal_D(L, d->couplings[s]);
+                std::vector<uint8_t> codes(8 * static_cast<size_t>(N), 0);
+                pack_bond_codes(L, d->couplings[s], D, codes.data());
+                PT_HIP(hipMemcpy(c->cpl6 + P.cpl6_base[s], codes.data(), codes.size(), hipMemcpyHostToDevice));
+                PT_HIP(hipMemcpy(c->bm_D + s, &D, sizeof(float), hipMemcpyHostToDevice));
+                continue;
+            }
             buf.assign(static_cast<size_t>(54 * N), 0.0f);
             if (P.lanes[s] == 1)
                 pack_couplings(L, d->couplings[s], buf.data());

@@ -102,7 +102,31 @@ __device__ __forceinline__ double update(const Gather &g, const float (&A)[54], 
            static_cast<double>(sz) * h[2];
 }
 
-template <int KIND, bool ENERGY>
+// The six matrices of a site from its bond codes (PT_F_BIMODAL): code bit 0
+// gives J = -1, bits 1..6 negative entries of D in the order 00, 11, 22,
+// 01, 02, 12; the diagonal is the FP32 sum J + d, so the values are those
+// of the matrices the codes were made from, bit for bit.  The family is
+// symmetric, so a backward matrix needs no transpose.
+__device__ __forceinline__ void decode_bonds(uint32_t lo, uint32_t hi, float D, float (&A)[54])
+{
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        const uint32_t code = ((n < 4 ? lo >> (8 * n) : hi >> (8 * (n - 4)))) & 0x7fu;
+        const float J = (code & 1u) ? -1.0f : 1.0f;
+        float d[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d[k] = ((code >> (1 + k)) & 1u) ? -D : D;
+        float *m = A + 9 * n;
+        m[0] = J + d[0];
+        m[4] = J + d[1];
+        m[8] = J + d[2];
+        m[1] = m[3] = d[3];
+        m[2] = m[6] = d[4];
+        m[5] = m[7] = d[5];
+    }
+}
+
+template <int KIND, bool ENERGY, bool BM>
 __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
 {
     constexpr bool kOwn = KIND != kHeatbath;  // heat-bath ignores the old spin
@@ -123,7 +147,11 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
         off.n[n] = 4u * (static_cast<unsigned>(1 - c) * 3u * H + static_cast<unsigned>(nb.idx[n]));
 
     float A[54];
-    {
+    if constexpr (BM) {
+        const Rsrc rc = make_rsrc(P.cpl + P.cpl_base[s] + static_cast<int64_t>(c) * 2 * H, 2u * H4);
+        const unsigned o = 8u * static_cast<unsigned>(pc);
+        decode_bonds(__float_as_uint(ld(rc, o, 0)), __float_as_uint(ld(rc, o, 4)), P.bm_D[s], A);
+    } else {
         const Rsrc rc = make_rsrc(P.cpl + P.cpl_base[s] + static_cast<int64_t>(c) * 54 * H, 54u * H4);
         const unsigned o = 4u * static_cast<unsigned>(pc);
 #pragma unroll
@@ -273,16 +301,19 @@ hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_
 {
     const dim3 grid(kXcds * p.per, (p.C + p.G - 1) / p.G, n_samples);
     const dim3 block(kSweepBlock);
-    if (kind == kOverrelax) {
-        if (energy) return launch_kernel(half_sweep_kernel<kOverrelax, true>, grid, block, 0, st, t, p);
-        else return launch_kernel(half_sweep_kernel<kOverrelax, false>, grid, block, 0, st, t, p);
-    } else if (kind == kHeatbath) {
-        if (energy) return launch_kernel(half_sweep_kernel<kHeatbath, true>, grid, block, 0, st, t, p);
-        else return launch_kernel(half_sweep_kernel<kHeatbath, false>, grid, block, 0, st, t, p);
-    } else {
-        return launch_kernel(half_sweep_kernel<kEnergyOnly, true>, grid, block, 0, st, t, p);
+    auto go = [&](auto kernel) { return launch_kernel(kernel, grid, block, 0, st, t, p); };
+    if (p.bimodal) {
+        if (kind == kOverrelax)
+            return energy ? go(half_sweep_kernel<kOverrelax, true, true>) : go(half_sweep_kernel<kOverrelax, false, true>);
+        if (kind == kHeatbath)
+            return energy ? go(half_sweep_kernel<kHeatbath, true, true>) : go(half_sweep_kernel<kHeatbath, false, true>);
+        return go(half_sweep_kernel<kEnergyOnly, true, true>);
     }
-    return hipGetLastError();
+    if (kind == kOverrelax)
+        return energy ? go(half_sweep_kernel<kOverrelax, true, false>) : go(half_sweep_kernel<kOverrelax, false, false>);
+    if (kind == kHeatbath)
+        return energy ? go(half_sweep_kernel<kHeatbath, true, false>) : go(half_sweep_kernel<kHeatbath, false, false>);
+    return go(half_sweep_kernel<kEnergyOnly, true, false>);
 }
 
 hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st)

@@ -125,3 +125,36 @@ def test_checkpoint_calls_need_a_context(lib):
     n = C.c_size_t()
     assert lib.pt_save(None, None, 0, C.byref(n)) == ptsg.PT_ESTATE
     assert lib.pt_load(None, None, 0) == ptsg.PT_ESTATE
+
+
+def test_bimodal_flag_validates_the_family(lib):
+    """PT_F_BIMODAL accepts the paper's family bit for bit (D = 0.5 and D = 1,
+    where diagonals can be exactly 0) and stores 8 bytes of codes per site
+    for site-lane samples instead of 54 floats; anything else is refused."""
+    L, T, R = 8, 4, 2
+    N = L ** 3
+    temps = [inputs.geometric_temps(0.5, 1.5, T)]
+    f = ptsg.PT_F_SITE_LANES
+    for D in (0.5, 1.0):
+        cpl = [inputs.bimodal_couplings(L, D, 3)]
+        plain = ptsg.pt_workspace_size([L], cpl, temps, R, flags=f)
+        packed = ptsg.pt_workspace_size([L], cpl, temps, R, flags=f | ptsg.PT_F_BIMODAL)
+        assert packed > 0
+        assert plain - packed == pytest.approx(4 * (54 - 2) * N, abs=4096)
+
+    def refused(M):
+        ok = ptsg.pt_workspace_size([L], [M], temps, R, flags=ptsg.PT_F_BIMODAL) > 0
+        return not ok and "PT_F_BIMODAL" in ptsg.pt_last_error()
+
+    assert refused(inputs.gaussian_couplings(L, 3))
+    base = inputs.bimodal_couplings(L, 1.0, 4)
+    M = base.copy()
+    M[1, 17, 0, 1] = -M[1, 17, 0, 1]          # asymmetric bond
+    assert refused(M)
+    M = base.copy()
+    M[2, 5, 1, 2] = M[2, 5, 2, 1] = 0.25      # another magnitude
+    assert refused(M)
+    M = base.copy()
+    mu, i, a = np.argwhere(M[..., [0, 1, 2], [0, 1, 2]] == 0)[0]   # D = 1: exact zeros
+    M[mu, i, a, a] = -0.0                     # equal as a number, other bits
+    assert refused(M)
