@@ -46,18 +46,26 @@ class OracleEnsemble:
             for j in range(self.T):
                 self.E[r, j] = O.energy(self.L, self.M, self.spins[r, j])
 
-    def step(self, n_hb, n_or):
-        """n_hb heat-bath sweeps then n_or overrelaxation sweeps, every chain."""
-        for r in range(self.R):
-            for j in range(self.T):
-                k = self.slot_of(r, j)
-                s = self.spins[r, j]
-                for n in range(n_hb):
-                    O.sweep(self.L, self.M, s, 1, self.beta[k], self.seed,
-                            self.hb_sweeps + n, self.sample, k, r)
-                for _ in range(n_or):
-                    O.sweep(self.L, self.M, s, 0, self.beta[k], self.seed, 0,
-                            self.sample, k, r)
+    def _chain_sweeps(self, r, j, n_hb, n_or):
+        k = self.slot_of(r, j)
+        s = self.spins[r, j]
+        for n in range(n_hb):
+            O.sweep(self.L, self.M, s, 1, self.beta[k], self.seed,
+                    self.hb_sweeps + n, self.sample, k, r)
+        for _ in range(n_or):
+            O.sweep(self.L, self.M, s, 0, self.beta[k], self.seed, 0,
+                    self.sample, k, r)
+
+    def step(self, n_hb, n_or, pool=None):
+        """n_hb heat-bath sweeps then n_or overrelaxation sweeps, every chain.
+        Chains are independent within a step; with a thread pool (the C
+        calls release the GIL) they run concurrently, same result."""
+        jobs = [(r, j) for r in range(self.R) for j in range(self.T)]
+        if pool is None:
+            for r, j in jobs:
+                self._chain_sweeps(r, j, n_hb, n_or)
+        else:
+            list(pool.map(lambda rj: self._chain_sweeps(rj[0], rj[1], n_hb, n_or), jobs))
         self.hb_sweeps += n_hb
         self.update_energies()
 
