@@ -96,6 +96,31 @@ void or_half_sweep(int L, const double *M, double *s, int colour, int kind,
     }
 }
 
+/* Row-ordered overrelaxation sweep (the alternative deterministic order of
+ * Sec. III and appendix A.3: rows of 8 spins along x, updated one after the
+ * other inside a row, rows that share no bond updated together).  Reading
+ * taken: row (b, y, z) holds x = 8b .. 8b+7; its class is (b + y + z) mod 2;
+ * two rows of one class share no bond (neighbouring rows differ by one in
+ * exactly one of b, y, z), so the class-0 rows, then the class-1 rows, in
+ * any order.  Inside a row the sites go in increasing x, each seeing the
+ * spins already updated before it.  L must be a multiple of 8. */
+void or_row_sweep(int L, const double *M, double *s)
+{
+    const int B = L / 8;
+    for (int cls = 0; cls < 2; ++cls)
+        for (int z = 0; z < L; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int b = 0; b < B; ++b) {
+                    if (((b + y + z) & 1) != cls) continue;
+                    for (int x = 8 * b; x < 8 * b + 8; ++x) {
+                        const int i = x + L * (y + L * z);
+                        double h[3];
+                        or_local_field(L, M, s, i, h);
+                        or_overrelax_spin(h, s + 3 * i);
+                    }
+                }
+}
+
 /* Hot start: z = 1 - 2 u1 is uniform on [-1, 1] and the azimuth uniform,
  * which is the uniform law on the sphere (Archimedes). */
 void or_init_spins(int L, double *s, uint64_t seed, uint32_t sample,

@@ -15,7 +15,7 @@ from . import oracle as O
 
 
 class OracleEnsemble:
-    def __init__(self, L, couplings, temps, n_replicas, seed, sample=0, spins=None):
+    def __init__(self, L, couplings, temps, n_replicas, seed, sample=0, spins=None, row_or=False):
         self.L = int(L)
         self.N = self.L ** 3
         self.M = np.ascontiguousarray(np.asarray(couplings, dtype=np.float32)
@@ -25,6 +25,7 @@ class OracleEnsemble:
         self.T = len(self.temps)
         self.R = int(n_replicas)
         self.seed = int(seed)
+        self.row_or = bool(row_or)   # overrelaxation in the row order (oracle.row_sweep)
         self.sample = int(sample)
         self.hb_sweeps = 0
         self.pt_passes = 0
@@ -53,8 +54,11 @@ class OracleEnsemble:
             O.sweep(self.L, self.M, s, 1, self.beta[k], self.seed,
                     self.hb_sweeps + n, self.sample, k, r)
         for _ in range(n_or):
-            O.sweep(self.L, self.M, s, 0, self.beta[k], self.seed, 0,
-                    self.sample, k, r)
+            if self.row_or:
+                O.row_sweep(self.L, self.M, s)
+            else:
+                O.sweep(self.L, self.M, s, 0, self.beta[k], self.seed, 0,
+                        self.sample, k, r)
 
     def step(self, n_hb, n_or, pool=None):
         """n_hb heat-bath sweeps then n_or overrelaxation sweeps, every chain.

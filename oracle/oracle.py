@@ -43,6 +43,7 @@ def lib():
                                     C.c_uint32]
         L.or_init_spins.argtypes = [C.c_int, _dp, C.c_uint64, C.c_uint32, C.c_uint32,
                                     C.c_uint32]
+        L.or_row_sweep.argtypes = [C.c_int, _dp, _dp]
         L.or_pt_pass.argtypes = [C.c_int, _dp, _dp, _i32p, C.c_uint64, C.c_uint32,
                                  C.c_uint32, C.c_uint32]
         L.or_pt_pass.restype = C.c_int
@@ -147,6 +148,13 @@ def pt_pass(beta, E, perm, seed, pass_index, sample, rep):
     assert perm.dtype == np.int32 and perm.flags.c_contiguous
     return lib().or_pt_pass(len(beta), _d(beta), _d(E), perm.ctypes.data_as(_i32p),
                             int(seed), int(pass_index), int(sample), int(rep))
+
+
+def row_sweep(L, M, s):
+    """Row-ordered overrelaxation sweep, in place (s: float64 [N][3])."""
+    assert L % 8 == 0 and s.dtype == np.float64 and s.flags.c_contiguous
+    M = _f64(M)
+    lib().or_row_sweep(L, _d(M), _d(s))
 
 
 def overlaps(L, sa, sb):

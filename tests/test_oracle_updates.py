@@ -12,6 +12,9 @@ import numpy as np
 import pytest
 from scipy import stats
 
+import oracle as O
+from paper_1309_1599_amd import inputs
+
 
 def _cdf_cos(c, X):
     """CDF of c in [-1, 1] with density ~ exp(X c)."""
@@ -206,3 +209,66 @@ def test_schwinger_dyson_lattice_equilibrium(orc):
     blocks = vals[: len(vals) // 20 * 20].reshape(20, -1).mean(axis=1)
     err = blocks.std(ddof=1) / np.sqrt(len(blocks))
     assert abs(vals.mean()) < 4 * err, (vals.mean(), err)
+
+
+# ---- row-ordered overrelaxation (the paper's alternative deterministic order)
+
+def _row_sweep_by_hand(L, M, s):
+    """The row order written out with single-site calls: class 0 rows, then
+    class 1, each row in increasing x."""
+    for cls in (0, 1):
+        for z in range(L):
+            for y in range(L):
+                for b in range(L // 8):
+                    if (b + y + z) % 2 != cls:
+                        continue
+                    for x in range(8 * b, 8 * b + 8):
+                        i = x + L * (y + L * z)
+                        h = O.local_field(L, M, s, i)
+                        s[i] = O.overrelax_spin(h, s[i])
+
+
+def test_row_sweep_is_the_stated_order():
+    L = 8
+    M = inputs.gaussian_couplings(L, 41).astype(np.float64)
+    s0 = O.init_spins(L, 41, 0, 0, 0)
+    a = s0.copy()
+    O.row_sweep(L, M, a)
+    b = s0.copy()
+    _row_sweep_by_hand(L, M, b)
+    np.testing.assert_array_equal(a, b)
+    # it is not the checkerboard sweep
+    c = s0.copy()
+    O.sweep(L, M, c, 0, 1.0, 41, 0, 0, 0, 0)
+    assert np.abs(a - c).max() > 1e-3
+
+
+def test_row_sweep_rows_of_a_class_commute():
+    """Rows of one class share no bond: updating them in reverse order gives
+    the same spins (bit for bit), while reversing x inside a row does not."""
+    L = 16
+    M = inputs.gaussian_couplings(L, 42).astype(np.float64)
+    s0 = O.init_spins(L, 42, 0, 0, 0)
+    a = s0.copy()
+    O.row_sweep(L, M, a)
+    b = s0.copy()
+    for cls in (0, 1):
+        rows = [(b_, y, z) for z in range(L) for y in range(L) for b_ in range(L // 8) if (b_ + y + z) % 2 == cls]
+        for b_, y, z in reversed(rows):
+            for x in range(8 * b_, 8 * b_ + 8):
+                i = x + L * (y + L * z)
+                b[i] = O.overrelax_spin(O.local_field(L, M, b, i), b[i])
+    np.testing.assert_array_equal(a, b)
+
+
+def test_row_sweep_conserves_energy():
+    """Each single-spin overrelaxation keeps s.h, and s_i enters E only
+    through -s_i.h_i, so any order conserves E (to rounding)."""
+    L = 16
+    M = inputs.gaussian_couplings(L, 43).astype(np.float64)
+    s = O.init_spins(L, 43, 0, 0, 0)
+    E0 = O.energy(L, M, s)
+    for _ in range(5):
+        O.row_sweep(L, M, s)
+    assert abs(O.energy(L, M, s) - E0) <= 1e-12 * abs(E0) * 5
+    assert np.abs(np.linalg.norm(s, axis=1) - 1).max() < 1e-14
