@@ -28,7 +28,7 @@ PEAK_FP32_TFLOPS = 78.6     # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 flops 
 FLOPS_PER_SU = 138          # overrelaxation update: 54-term field, reflection, renormalisation
 METRIC = "ps per spin update (all chains) & HBM roofline %, batched FP32 vs plain FP64"
 KERNEL_SOURCES = ["paper_1309_1599_amd/csrc/sweep.hip", "paper_1309_1599_amd/csrc/sweep_cl.hip",
-                  "paper_1309_1599_amd/csrc/sweep_rs.hip",
+                  "paper_1309_1599_amd/csrc/sweep_rs.hip", "paper_1309_1599_amd/csrc/sweep_row.hip",
                   "paper_1309_1599_amd/csrc/spin_update.hpp", "paper_1309_1599_amd/csrc/kernels.hpp",
                   "paper_1309_1599_amd/csrc/philox.hpp"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "overrelax_half_sweep_{preset}_pmc.txt")

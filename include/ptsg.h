@@ -152,7 +152,16 @@ enum {
      * (8 bytes per site instead of 216) and decode it in the sweep kernel;
      * results are bit-identical to passing the same matrices without the
      * flag.  Chain-lane and resident samples keep their float layouts. */
-    PT_F_BIMODAL = 64u
+    PT_F_BIMODAL = 64u,
+    /* Overrelaxation sweeps in the row order (Sec. III, appendix A.3) instead
+     * of the checkerboard: rows of 8 spins along x, row (b, y, z) holding
+     * x = 8b .. 8b+7 in class (b + y + z) mod 2; a sweep updates every
+     * class-0 row, then every class-1 row, each row in increasing x with
+     * each spin seeing those updated before it.  Heat-bath sweeps stay
+     * checkerboard.  Needs L a multiple of 8 and <= 128 and runs on the
+     * chain-lane mapping (excludes PT_F_SITE_LANES, PT_F_RESIDENT,
+     * PT_F_PLAIN). */
+    PT_F_ROW_OR = 128u
 };
 
 /* The mapping used for a sample: PT_F_SITE_LANES, PT_F_CHAIN_LANES or

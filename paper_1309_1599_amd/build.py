@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libptsg.so")
-SOURCES = ["sweep.hip", "sweep_cl.hip", "sweep_rs.hip", "tempering.hip", "measure.hip", "ptsg.hip"]
+SOURCES = ["sweep.hip", "sweep_cl.hip", "sweep_rs.hip", "sweep_row.hip", "tempering.hip", "measure.hip",
+           "ptsg.hip"]
 HEADERS = ["kernels.hpp", "philox.hpp", "spin_update.hpp"]
 ARCH = os.environ.get("PTSG_ARCH", "gfx950")
 

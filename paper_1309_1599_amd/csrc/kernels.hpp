@@ -173,6 +173,10 @@ hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_
                              hipStream_t st, const LaunchTiming &t = {});
 hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_items,
                                 hipStream_t st, const LaunchTiming &t = {});
+// Row-ordered overrelaxation (chain-lane layout): one launch per row class.
+int row_waves(int L);
+hipError_t launch_cl_row_or(const ClParams &p, int cls, int n_items, hipStream_t st,
+                            const LaunchTiming &t = {});
 hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st,
                                 const LaunchTiming &t = {});
 int rs_block(int L);

@@ -124,6 +124,7 @@ int choose_strip(int L)
 int choose_mapping(const pt_batch_desc *d, int s)
 {
     const int L = d->L[s], C = d->n_replicas * d->n_temps[s];
+    if (d->flags & PT_F_ROW_OR) return kChainLanes;  // the row-order kernel is chain-lane
     if (d->flags & (PT_F_SITE_LANES | PT_F_PLAIN)) return kSiteLanes;
     if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
     if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
@@ -192,6 +193,8 @@ std::string validate(const pt_batch_desc *d)
     if (!d) return "descriptor is NULL";
     if (d->n_samples < 1) return "n_samples must be >= 1";
     if (!d->L || !d->n_temps || !d->temps || !d->couplings) return "NULL array in descriptor";
+    if ((d->flags & PT_F_ROW_OR) && (d->flags & (PT_F_SITE_LANES | PT_F_RESIDENT | PT_F_PLAIN)))
+        return "PT_F_ROW_OR runs on the chain-lane mapping: it excludes PT_F_SITE_LANES, PT_F_RESIDENT and PT_F_PLAIN";
     if (d->n_replicas < 1 || d->n_replicas > 256) return "n_replicas must be in [1, 256]";
     for (int s = 0; s < d->n_samples; ++s) {
         const int L = d->L[s];
@@ -207,6 +210,8 @@ std::string validate(const pt_batch_desc *d)
             if (k > 0 && !(t > d->temps[s][k - 1]))
                 return "sample " + std::to_string(s) + ": temperatures must be strictly ascending";
         }
+        if ((d->flags & PT_F_ROW_OR) && (L % 8 != 0 || L > 128))
+            return "sample " + std::to_string(s) + ": PT_F_ROW_OR needs L a multiple of 8 and <= 128";
         if ((d->flags & PT_F_BIMODAL) && bimodal_D(L, d->couplings[s]) == 0.0f)
             return "sample " + std::to_string(s) +
                    ": PT_F_BIMODAL needs every bond to be J*1 + D_sym with J = +-1 and D_ab = +-D, D > 0";
@@ -328,6 +333,7 @@ struct pt_ctx {
     uint32_t *counters = nullptr;     // device: heat-bath sweeps, PT passes
     float *bm_D = nullptr;            // device, per sample: D of the bimodal family (PT_F_BIMODAL)
     bool use_graphs = false;
+    bool row_or = false;              // PT_F_ROW_OR: overrelaxation sweeps in the row order
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
     int *d_L = nullptr, *d_T = nullptr, *d_chain_base = nullptr, *d_perm_base = nullptr,
@@ -527,6 +533,26 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
             uint32_t hb = 0;
             for (int n = 0; n < total; ++n) {
                 const int kind = kinds[n];
+                if (kind == kOverrelax && c->row_or) {
+                    // row order: class 0 rows, then class 1; energies after the last sweep
+                    ClParams p = cl_params(c, k, first, 0, hb);
+                    const int tiles = (row_waves(k.L) + kClWaves - 1) / kClWaves;
+                    p.per = (tiles + 7) / 8;   // grid = 8 XCDs x per
+                    for (int cls = 0; cls < 2; ++cls) {
+                        st = timed_launch(c, kind, [&](const LaunchTiming &t) {
+                            return launch_cl_row_or(p, cls, cnt, c->stream, t);
+                        });
+                        if (st != PT_OK) return st;
+                    }
+                    if (n == total - 1) {
+                        const ClParams q = cl_params(c, k, first, 1, hb);
+                        st = timed_launch(c, kEnergyOnly, [&](const LaunchTiming &t) {
+                            return launch_cl_half_sweep(kEnergyOnly, true, q, cnt, c->stream, t);
+                        });
+                        if (st != PT_OK) return st;
+                    }
+                    continue;
+                }
                 for (int colour = 0; colour < 2; ++colour) {
                     const bool energy = n == total - 1 && colour == 1;
                     const ClParams p = cl_params(c, k, first, colour, hb);
@@ -655,7 +681,7 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
 // The autotuner runs only when no mapping is forced by a flag.
 static bool wants_autotune(const pt_batch_desc *d)
 {
-    const unsigned forced = PT_F_SITE_LANES | PT_F_CHAIN_LANES | PT_F_RESIDENT | PT_F_PLAIN;
+    const unsigned forced = PT_F_SITE_LANES | PT_F_CHAIN_LANES | PT_F_RESIDENT | PT_F_PLAIN | PT_F_ROW_OR;
     return (d->flags & PT_F_AUTOTUNE) && !(d->flags & forced);
 }
 
@@ -745,6 +771,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     c->counters = reinterpret_cast<uint32_t *>(w + P.off_counters);
     c->bm_D = reinterpret_cast<float *>(w + P.off_bmD);
     c->use_graphs = (d->flags & PT_F_GRAPHS) != 0;
+    c->row_or = (d->flags & PT_F_ROW_OR) != 0;
     {
         const uint32_t zero[2] = {0u, 0u};
         PT_HIP(hipMemcpy(c->counters, zero, sizeof(zero), hipMemcpyHostToDevice));

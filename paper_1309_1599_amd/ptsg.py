@@ -18,6 +18,7 @@ PT_M_OVERLAP, PT_M_CHIRAL, PT_M_SD, PT_M_ALL = 1, 2, 4, 7
 PT_K_OVERRELAX, PT_K_HEATBATH, PT_K_RESIDENT = 0, 1, 2
 PT_F_SITE_LANES, PT_F_CHAIN_LANES, PT_F_RESIDENT, PT_F_GRAPHS, PT_F_PLAIN, PT_F_AUTOTUNE, PT_F_BIMODAL = \
     1, 2, 4, 8, 16, 32, 64
+PT_F_ROW_OR = 128
 
 # numpy view of the C struct pt_meas (744 bytes, no padding)
 MEAS_DTYPE = np.dtype([

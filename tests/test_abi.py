@@ -158,3 +158,15 @@ def test_bimodal_flag_validates_the_family(lib):
     mu, i, a = np.argwhere(M[..., [0, 1, 2], [0, 1, 2]] == 0)[0]   # D = 1: exact zeros
     M[mu, i, a, a] = -0.0                     # equal as a number, other bits
     assert refused(M)
+
+
+def test_row_order_flag_validation(lib):
+    temps = [inputs.geometric_temps(0.5, 1.5, 3)]
+    ok = ptsg.pt_workspace_size([16], [np.zeros((3, 16 ** 3, 3, 3), np.float32)], temps, 2,
+                                flags=ptsg.PT_F_ROW_OR)
+    assert ok > 0
+    for L, flags in ((12, ptsg.PT_F_ROW_OR), (16, ptsg.PT_F_ROW_OR | ptsg.PT_F_SITE_LANES),
+                     (16, ptsg.PT_F_ROW_OR | ptsg.PT_F_PLAIN)):
+        cpl = [np.zeros((3, L ** 3, 3, 3), np.float32)]
+        assert ptsg.pt_workspace_size([L], cpl, temps, 2, flags=flags) == 0
+        assert "PT_F_ROW_OR" in ptsg.pt_last_error()
