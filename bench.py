@@ -170,6 +170,8 @@ def main():
                     help="gaussian: 9 iid N(0,1) entries per bond (the workload); bimodal: the paper's "
                          "family J*1 + D_sym, J = +-1, D_ab = +-0.5, stored as one byte per bond "
                          "(PT_F_BIMODAL) where the mapping allows")
+    ap.add_argument("--or-order", choices=("checkerboard", "rows"), default="checkerboard",
+                    help="rows: overrelaxation in the row order (PT_F_ROW_OR, chain-lane mapping)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path does not "
@@ -197,6 +199,9 @@ def main():
         flags |= ptsg.PT_F_GRAPHS
     if bimodal:
         flags |= ptsg.PT_F_BIMODAL
+    rows = args.or_order == "rows"
+    if rows:
+        flags = (flags & ~(ptsg.PT_F_SITE_LANES | ptsg.PT_F_RESIDENT | ptsg.PT_F_AUTOTUNE)) | ptsg.PT_F_ROW_OR
     L = Ls[0]
     C = R * len(temps[0])
 
@@ -223,7 +228,8 @@ def main():
         su_per_launch = or_su / max(1, n_l)
         avg_s = ms / max(1, n_l) / 1e3
         achieved = bytes_per_su * su_per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": ("cl_half_sweep_kernel<overrelax>" if mapping == "chain"
+        roof = {"bound": "hbm", "kernel": ("cl_row_or_kernel" if rows else
+                                           "cl_half_sweep_kernel<overrelax>" if mapping == "chain"
                                            else "half_sweep_kernel<overrelax>"),
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": pmc_traffic(args.preset, mapping, kernel_hash()),
@@ -270,6 +276,7 @@ def main():
             "mapping": (mapping + " lanes" if not mixed else
                         {str(Lv): maps[Ls.index(Lv)] + " lanes" for Lv in sorted(set(Ls))}),
             "mapping_choice": args.mapping,
+            "overrelaxation_order": args.or_order,
             "graphs": not args.no_graphs,
         },
         "roofline": roof,
@@ -293,7 +300,7 @@ def main():
             per_L[str(Lv)] = {"ps_per_su": round(w / (max(2, args.steps) * su) * 1e12, 3),
                               "mapping": m[0] + " lanes"}
         result["per_L_separate_contexts"] = per_L
-    elif not args.no_plain:
+    elif not args.no_plain and not rows:   # the plain form is checkerboard only
         pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS) | (ptsg.PT_F_BIMODAL if bimodal else 0)
         w, su, _, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
                           timing=False)

@@ -89,25 +89,36 @@ __global__ __launch_bounds__(kClBlock) void cl_row_or_kernel(ClParams P, int cls
     const int x0 = 8 * b;
     const int xl = x0 == 0 ? L - 1 : x0 - 1;          // -x neighbour of the first site
     const int xr = x0 + 8 == L ? 0 : x0 + 8;          // +x neighbour of the last site
+    // Software pipeline: the loads of site k+1 (its +x, y and z neighbours,
+    // none of which is written by site k) are issued before site k is
+    // stored, so they are in flight while site k is updated.
+    struct Gather {
+        float n[6][3];  // n[1] (-x) is filled from registers
+    };
+    auto gather = [&](Gather &gt, int k) {
+        const int x = x0 + k;
+        if (k < 7) load3(gt.n[0], r, voff, site(x + 1, y, z));
+        else if (B != 1) load3(gt.n[0], r, voff, site(xr, y, z));
+        load3(gt.n[2], r, voff, site(x, yp, z));
+        load3(gt.n[3], r, voff, site(x, ym, z));
+        load3(gt.n[4], r, voff, site(x, y, zp));
+        load3(gt.n[5], r, voff, site(x, y, zm));
+    };
     float prev[3], cur[3], first[3];
     load3(prev, r, voff, site(xl, y, z));
     load3(cur, r, voff, site(x0, y, z));
-#pragma unroll 1
+    Gather ga, gb;
+    gather(ga, 0);
+#pragma unroll
     for (int k = 0; k < 8; ++k) {
+        Gather &g0 = (k & 1) ? gb : ga;
+        Gather &g1 = (k & 1) ? ga : gb;
+        if (k < 7) gather(g1, k + 1);
         const int x = x0 + k;
-        float sn[6][3];
-        if (k < 7) {
-            load3(sn[0], r, voff, site(x + 1, y, z));
-        } else if (B == 1) {
-            sn[0][0] = first[0]; sn[0][1] = first[1]; sn[0][2] = first[2];
-        } else {
-            load3(sn[0], r, voff, site(xr, y, z));
+        if (k == 7 && B == 1) {   // the row is the whole x line: +x of x = 7 is the updated x = 0
+            g0.n[0][0] = first[0]; g0.n[0][1] = first[1]; g0.n[0][2] = first[2];
         }
-        load3(sn[2], r, voff, site(x, yp, z));
-        load3(sn[3], r, voff, site(x, ym, z));
-        load3(sn[4], r, voff, site(x, y, zp));
-        load3(sn[5], r, voff, site(x, y, zm));
-        sn[1][0] = prev[0]; sn[1][1] = prev[1]; sn[1][2] = prev[2];
+        g0.n[1][0] = prev[0]; g0.n[1][1] = prev[1]; g0.n[1][2] = prev[2];
         const CFloat *A = M + cpl_block(x);
         const v16f a0 = *(CV16 *)(A);
         const v16f a1 = *(CV16 *)(A + 16);
@@ -116,7 +127,7 @@ __global__ __launch_bounds__(kClBlock) void cl_row_or_kernel(ClParams P, int cls
         const v2f a4 = *(CV2 *)(A + 52);
         asm volatile("" ::"s"(a0), "s"(a1), "s"(a2), "s"(a3), "s"(a4));
         float h[3];
-        local_field(sn, [&](int n, int a, int bb) {
+        local_field(g0.n, [&](int n, int a, int bb) {
             const int q = n * 9 + a * 3 + bb;
             return q < 16 ? a0[q] : q < 32 ? a1[q - 16] : q < 48 ? a2[q - 32] : q < 52 ? a3[q - 48] : a4[q - 52];
         }, h);
@@ -131,7 +142,7 @@ __global__ __launch_bounds__(kClBlock) void cl_row_or_kernel(ClParams P, int cls
             first[0] = cur[0]; first[1] = cur[1]; first[2] = cur[2];
         }
         prev[0] = cur[0]; prev[1] = cur[1]; prev[2] = cur[2];
-        cur[0] = sn[0][0]; cur[1] = sn[0][1]; cur[2] = sn[0][2];
+        cur[0] = g0.n[0][0]; cur[1] = g0.n[0][1]; cur[2] = g0.n[0][2];
     }
 }
 
