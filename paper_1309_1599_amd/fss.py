@@ -1,0 +1,175 @@
+"""Finite-size-scaling runs on the library (Sec. III, Sec. IV).
+
+`simulate` runs one lattice size: a batch of disorder samples, each with
+N_T temperatures x R replicas, the paper's Monte Carlo step (1 heat-bath +
+L overrelaxation sweeps + 1 tempering pass) for a number of steps, and a
+measurement every few steps.  Per (sample, temperature slot) it keeps, for
+every logarithmic bin of the measurement series (the last half, the
+quarter before it, ...), the sums of q^2 and |q(k_min)|^2 of the scalar
+spin-glass overlap over the measurements and replica pairs of the bin.
+
+`analyse` turns two such runs (L and 2L on one temperature grid) into
+xi_L/L and xi_2L/(2L) from the last bin, with jackknife errors over samples
+(the correlation length is computed from the disorder-averaged
+susceptibilities, Sec. II.B), their crossing temperature from linear fits
+to the four temperatures nearest to it, xi/L at the crossing, nu from the
+ratio of the slopes of xi (Sec. IV), and the thermalisation test of
+Sec. III on chi(0) per bin.
+
+Run as  python -m paper_1309_1599_amd.fss --L 8 16 --samples 256 ...
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import analysis as A
+from . import inputs, ptsg
+
+
+def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimodal", D=1.0,
+             flags=ptsg.PT_F_GRAPHS | ptsg.PT_F_AUTOTUNE, log=print):
+    temps = np.asarray(temps, dtype=np.float64)
+    T = len(temps)
+    if couplings == "bimodal":
+        cpl = [inputs.bimodal_couplings(L, D, seed, s) for s in range(n_samples)]
+        flags |= ptsg.PT_F_BIMODAL
+    else:
+        cpl = [inputs.gaussian_couplings(L, seed, s) for s in range(n_samples)]
+    ctx = ptsg.pt_init_batch([L] * n_samples, cpl, [temps] * n_samples, R, seed, flags=flags)
+    del cpl
+    n_meas = steps // measure_every
+    bins = A.log_bins(n_meas)
+    which = np.full(n_meas, -1)
+    for i, (lo, hi) in enumerate(bins):
+        which[lo:hi] = i
+    nb = len(bins)
+    sums = {k: np.zeros((nb, n_samples, T)) for k in ("q2", "qk2", "e")}
+    counts = np.zeros(nb)
+    acc = np.zeros(n_samples)
+    t0 = time.perf_counter()
+    m = 0
+    for step in range(1, steps + 1):
+        ptsg.pt_step(ctx, 1, L)
+        ptsg.pt_swap(ctx)
+        if step % measure_every == 0:
+            recs = ptsg.pt_measure(ctx, ptsg.PT_M_OVERLAP)
+            b = which[m]
+            if b >= 0:
+                F = A.fields(recs[None], L)
+                s, k = recs["sample"], recs["tslot"]
+                for key in sums:
+                    np.add.at(sums[key][b], (s, k), F[key][0])
+                counts[b] += 1
+            m += 1
+        if step % max(1, steps // 20) == 0:
+            log(f"L={L}: step {step}/{steps} ({time.perf_counter() - t0:.0f} s)")
+    pairs = R * (R - 1) // 2
+    ptsg.pt_free(ctx)
+    means = {k: v / (counts[:, None, None] * pairs) for k, v in sums.items()}
+    return {"L": L, "temps": temps.tolist(), "R": R, "steps": steps, "measure_every": measure_every,
+            "n_samples": n_samples, "bins": bins, "counts": counts.tolist(),
+            "means": {k: v.tolist() for k, v in means.items()}, "seconds": time.perf_counter() - t0}
+
+
+def _blocks(run, b=0):
+    """(n_samples, 2, T) per-sample chi(0), chi(k_min) of bin b (0 = last)."""
+    N = run["L"] ** 3
+    q2 = np.asarray(run["means"]["q2"])[b]
+    qk2 = np.asarray(run["means"]["qk2"])[b]
+    return np.stack([N * q2, N * qk2], axis=1)
+
+
+def xi_over_L(run, b=0):
+    """xi/L per temperature from the disorder-averaged susceptibilities of
+    bin b, with jackknife errors over samples."""
+    L = run["L"]
+    return A.jackknife(_blocks(run, b), lambda m: A.xi_second_moment(m[0], m[1], L) / L)
+
+
+def analyse(small, large, n_fit=4):
+    """Crossing of xi/L between two runs on one temperature grid."""
+    T = np.asarray(small["temps"])
+    assert np.allclose(T, large["temps"]), "the two sizes need one temperature grid"
+    n = min(small["n_samples"], large["n_samples"])
+    Ls, Ll = small["L"], large["L"]
+    b1, b2 = _blocks(small)[:n], _blocks(large)[:n]   # sample i of each size forms block i
+
+    def f(m):
+        y1 = A.xi_second_moment(m[0], m[1], Ls) / Ls
+        y2 = A.xi_second_moment(m[2], m[3], Ll) / Ll
+        tc, yc, s1, s2 = A.crossing(T, y1, y2, n_fit=n_fit)
+        # d xi/dT = L d(xi/L)/dT
+        return np.array([tc, yc, (Ll * s2) / (Ls * s1)])
+
+    est, err = A.jackknife(np.concatenate([b1, b2], axis=1), f)
+    out = {"pair": [Ls, Ll], "T_cross": [est[0], err[0]], "xi_over_L_cross": [est[1], err[1]],
+           "slope_ratio": [est[2], err[2]]}
+    if Ll == 2 * Ls and est[2] > 2:
+        nu = A.nu_from_slope_ratio(est[2])
+        # error of nu from the jackknife of the ratio (propagated)
+        dnu = err[2] / (est[2] * np.log(2) * (np.log2(est[2]) - 1) ** 2)
+        out["nu"] = [nu, dnu]
+    return out
+
+
+def thermalisation(run):
+    """Sec. III test on chi_SG(0): per logarithmic bin (last first), the
+    disorder average of chi(0) minus that of the last bin, per temperature,
+    with jackknife errors over samples."""
+    N = run["L"] ** 3
+    q2 = N * np.asarray(run["means"]["q2"])        # (bins, samples, T)
+    out = []
+    for b in range(q2.shape[0]):
+        if run["counts"][b] == 0:
+            continue
+        d = q2[b] - q2[0]
+        m, e = A.jackknife(d)
+        out.append({"bin": run["bins"][b], "diff": m.tolist(), "err": e.tolist()})
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--L", type=int, nargs="+", default=[8, 16])
+    ap.add_argument("--samples", type=int, default=256)
+    ap.add_argument("--steps", type=int, nargs="+", default=[20480, 40960],
+                    help="Monte Carlo steps per size (one value, or one per size)")
+    ap.add_argument("--temps", type=float, nargs=3, default=[0.877, 1.28, 28], metavar=("TMIN", "TMAX", "N"))
+    ap.add_argument("--replicas", type=int, default=2)
+    ap.add_argument("--measure-every", type=int, default=10)
+    ap.add_argument("--couplings", choices=("bimodal", "gaussian"), default="bimodal")
+    ap.add_argument("--D", type=float, default=1.0)
+    ap.add_argument("--seed", type=int, default=1309)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    temps = inputs.geometric_temps(args.temps[0], args.temps[1], int(args.temps[2]))
+    steps = args.steps * len(args.L) if len(args.steps) == 1 else args.steps
+    runs = []
+    for L, n in zip(args.L, steps):
+        runs.append(simulate(L, args.samples, temps, args.replicas, n, args.measure_every,
+                             args.seed + L, args.couplings, args.D,
+                             log=lambda msg: print(msg, file=sys.stderr, flush=True)))
+    result = {"runs": [{k: r[k] for k in ("L", "n_samples", "steps", "seconds")} for r in runs],
+              "temps": temps.tolist(), "couplings": args.couplings, "D": args.D,
+              "xi_over_L": {str(r["L"]): [v.tolist() for v in xi_over_L(r)] for r in runs},
+              "thermalisation_chi0": {str(r["L"]): thermalisation(r) for r in runs},
+              "crossings": []}
+    for a, b in zip(runs, runs[1:]):
+        try:
+            result["crossings"].append(analyse(a, b))
+        except ValueError as e:
+            result["crossings"].append({"pair": [a["L"], b["L"]], "error": str(e)})
+    text = json.dumps(result, default=float)
+    if args.out:
+        with open(args.out, "w") as fh:
+            fh.write(text)
+    print(json.dumps(result["crossings"], default=float))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,51 @@
+"""CPU checks of the FSS post-processing (paper_1309_1599_amd.fss) on
+synthetic runs whose xi_L/L curves are known lines through a common point."""
+import numpy as np
+import pytest
+
+from paper_1309_1599_amd import fss
+
+
+def _run(L, T, xi_over_L, n_samples, noise, seed):
+    """A run dict whose per-sample susceptibilities give xi/L = xi_over_L(T)
+    in the disorder average (lattice Ornstein-Zernike form), with
+    multiplicative sample noise."""
+    rng = np.random.default_rng(seed)
+    N = L ** 3
+    chi0 = 10.0 * (1 + noise * rng.normal(size=(n_samples, len(T))))
+    xi = xi_over_L * L
+    chik = chi0 / (1 + 4 * xi ** 2 * np.sin(np.pi / L) ** 2)
+    q2 = np.stack([chi0 / N, chi0 / N * 1.01])          # last bin, then an earlier one
+    qk2 = np.stack([chik / N, chik / N])
+    return {"L": L, "temps": list(T), "n_samples": n_samples, "bins": [(5, 10), (2, 5)],
+            "counts": [5, 3], "means": {"q2": q2.tolist(), "qk2": qk2.tolist(), "e": np.zeros_like(q2).tolist()}}
+
+
+def test_crossing_nu_and_xi_at_the_crossing():
+    T = np.linspace(0.8, 1.2, 12)
+    Tc, yc, nu = 0.95, 0.6, 2.0
+    s1 = -0.8                                    # d(xi_L/L)/dT
+    # (d xi_2L/dT)/(d xi_L/dT) = 2^(1+1/nu)  =>  d(xi_2L/2L)/dT = s1 * 2^(1+1/nu) / 2
+    s2 = s1 * 2 ** (1 + 1 / nu) / 2
+    a = _run(8, T, yc + s1 * (T - Tc), 64, 0.0, 1)
+    b = _run(16, T, yc + s2 * (T - Tc), 64, 0.0, 2)
+    res = fss.analyse(a, b)
+    assert res["T_cross"][0] == pytest.approx(Tc, abs=1e-9)
+    assert res["xi_over_L_cross"][0] == pytest.approx(yc, abs=1e-9)
+    assert res["nu"][0] == pytest.approx(nu, rel=1e-6)
+    # with sample noise the estimate scatters within its jackknife error
+    a = _run(8, T, yc + s1 * (T - Tc), 200, 0.02, 3)
+    b = _run(16, T, yc + s2 * (T - Tc), 200, 0.02, 4)
+    res = fss.analyse(a, b)
+    assert abs(res["T_cross"][0] - Tc) < 5 * res["T_cross"][1] + 1e-3
+    assert res["T_cross"][1] > 0
+
+
+def test_xi_over_L_and_thermalisation():
+    T = np.linspace(0.8, 1.2, 5)
+    r = _run(8, T, np.full(5, 0.5), 16, 0.0, 5)
+    xi, err = fss.xi_over_L(r)
+    np.testing.assert_allclose(xi, 0.5, rtol=1e-12)
+    th = fss.thermalisation(r)
+    assert th[0]["diff"] == pytest.approx([0.0] * 5)
+    assert np.allclose(th[1]["diff"], 0.01 * 10.0)   # the earlier bin was 1 % higher
