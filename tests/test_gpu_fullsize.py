@@ -110,12 +110,16 @@ def test_fullsize_measure_sampled_records(big):
         assert abs(g["sd1_a"] - sd1) <= 1e-12 * abs(sd1) and abs(g["sd2_a"] - sd2) <= 1e-12 * abs(sd2)
 
 
-def test_largest_lattice_single_chain():
-    """L = 128 (N = 2^21), the largest size exercised: indexing beyond the
-    presets' range, sampled sites of one overrelaxation sweep."""
-    L, seed = 128, 901
+@pytest.mark.parametrize("L,flags", [(128, 0), (128, ptsg.PT_F_CHAIN_LANES), (256, 0)],
+                         ids=["128-site", "128-chain", "256-site"])
+def test_largest_lattice_single_chain(L, flags):
+    """L = 128 (N = 2^21) in both sweep mappings and L = 256 (N = 2^24, the
+    largest size the library accepts): indexing beyond the presets' range,
+    sampled sites of one overrelaxation sweep, corners and faces of the
+    periodic box included."""
+    seed = 901
     cpl = inputs.gaussian_couplings(L, seed)
-    ctx = ptsg.pt_init_batch([L], [cpl], [[1.0]], 1, seed)
+    ctx = ptsg.pt_init_batch([L], [cpl], [[1.0]], 1, seed, flags=flags)
     before = ptsg.pt_get_spins(ctx, 0, 0, 0)
     ptsg.pt_step(ctx, 0, 1)
     after = ptsg.pt_get_spins(ctx, 0, 0, 0)
