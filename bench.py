@@ -300,6 +300,17 @@ def main():
             per_L[str(Lv)] = {"ps_per_su": round(w / (max(2, args.steps) * su) * 1e12, 3),
                               "mapping": m[0] + " lanes"}
         result["per_L_separate_contexts"] = per_L
+        # every lattice in its own context (one sample per launch), one step
+        # each after one warm-up step: the unbatched reference
+        tot_s = tot_su = 0.0
+        for i in range(len(Ls)):
+            w, su, _, _ = run(ptsg, torch, [Ls[i]], [cpl[i]], [temps[i]], R, seed, flags & ~ptsg.PT_F_AUTOTUNE,
+                              n_hb, n_or, 0, 1, 1, timing=False)
+            tot_s += w
+            tot_su += su
+        per_lattice = tot_s / tot_su * 1e12
+        result["one_lattice_per_context"] = {"value": round(per_lattice, 3), "unit": "ps/SU",
+                                             "speedup_of_value": round(per_lattice / ps_per_su, 3)}
     elif not args.no_plain and not rows:   # the plain form is checkerboard only
         pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS) | (ptsg.PT_F_BIMODAL if bimodal else 0)
         w, su, _, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
