@@ -199,8 +199,8 @@ pt_status pt_swap(pt_ctx *ctx);
 /* Measure every (sample, slot, replica pair a < b) and copy the records,
  * ordered by sample, slot, then pair, into out[cap].  *n_out receives the
  * record count (sum over samples of n_temps * R(R-1)/2); PT_ENOMEM if cap is
- * smaller.  PT_M_OVERLAP / PT_M_CHIRAL need n_replicas >= 2 (PT_ESTATE).
- * Synchronous. */
+ * smaller; out == NULL with cap == 0 only stores the count.  PT_M_OVERLAP /
+ * PT_M_CHIRAL need n_replicas >= 2 (PT_ESTATE).  Synchronous. */
 pt_status pt_measure(pt_ctx *ctx, unsigned what, pt_meas *out, size_t cap, size_t *n_out);
 
 /* Spins of the chain at (sample, replica, slot), host [N][3] FP32.

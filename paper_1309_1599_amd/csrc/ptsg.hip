@@ -1129,6 +1129,7 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
         return fail(PT_ESTATE, "overlap and chirality need n_replicas >= 2");
     if (n_out) *n_out = static_cast<size_t>(P.n_records);
     if (P.n_records == 0) return PT_OK;
+    if (!out && cap == 0) return PT_OK;   // size query
     if (!out) return fail(PT_EINVAL, "output buffer is NULL");
     if (cap < static_cast<size_t>(P.n_records))
         return fail(PT_ENOMEM, "output holds " + std::to_string(cap) + " records, " +
