@@ -139,8 +139,8 @@ enum {
     PT_F_PLAIN = 16u,
     /* Autotuner: for each distinct (L, n_temps) in the batch, time a step of
      * 1 heat-bath + min(L, 32) overrelaxation sweeps of every applicable
-     * mapping on a temporary context (up to four of those samples) and use
-     * the fastest; results are cached
+     * mapping on a temporary context (enough of those samples for 4096
+     * chains, at least 4, at most 2 GB of spins) and use the fastest; results are cached
      * for the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
      * Runs kernels on the current device, so pt_workspace_size needs the
      * device too when this flag is set. */

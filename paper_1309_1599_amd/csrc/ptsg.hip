@@ -936,7 +936,8 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
 
 // Autotuner: for each distinct (L, n_temps) of the batch, time a step of one
 // heat-bath and min(L, 32) overrelaxation sweeps of every applicable mapping
-// on a temporary context holding up to four of those samples (best of two,
+// on a temporary context holding a representative share of those samples
+// (enough for 4096 chains, at least 4, at most 2 GB of spins; best of two,
 // after a warm-up step), and keep the fastest.  The step is long enough for
 // the chain-lane order to pay for its first, cold pass through the cache.  Results are cached per (device, L, n_temps, n_replicas,
 // samples timed, graphs) for the process.
@@ -952,7 +953,13 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
     for (int s = 0; s < d->n_samples; ++s) classes[{d->L[s], d->n_temps[s]}].push_back(s);
     for (auto &cl : classes) {
         const int L = cl.first.first;
-        const int n = std::min<int>(4, static_cast<int>(cl.second.size()));
+        // a representative batch: enough samples for >= 4096 chains (at least
+        // 4), at most 2 GB of spins per candidate context
+        const int64_t C = static_cast<int64_t>(d->n_replicas) * cl.first.second;
+        const int64_t chain_bytes = 12 * static_cast<int64_t>(L) * L * L;
+        int n = static_cast<int>(std::max<int64_t>(4, (4096 + C - 1) / C));
+        while (n > 1 && n * C * chain_bytes > (2ll << 30)) --n;
+        n = std::min<int>(n, static_cast<int>(cl.second.size()));
         const auto key = std::make_tuple(dev, L, cl.first.second, d->n_replicas, n, graphs != 0);
         int best = L > 128 ? kSiteLanes : -1;  // the only mapping beyond L = 128
         {
