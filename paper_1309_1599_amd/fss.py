@@ -17,6 +17,8 @@ ratio of the slopes of xi (Sec. IV), and the thermalisation test of
 Sec. III on chi(0) per bin.
 
 Run as  python -m paper_1309_1599_amd.fss --L 8 16 --samples 256 ...
+(--save FILE.npz keeps the per-sample bin means; --combine A.npz B.npz ...
+analyses several such runs of independent samples together.)
 """
 import argparse
 import json
@@ -48,7 +50,6 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
     nb = len(bins)
     sums = {k: np.zeros((nb, n_samples, T)) for k in ("q2", "qk2", "e")}
     counts = np.zeros(nb)
-    acc = np.zeros(n_samples)
     t0 = time.perf_counter()
     m = 0
     for step in range(1, steps + 1):
@@ -131,6 +132,56 @@ def thermalisation(run):
     return out
 
 
+def save_runs(path, runs):
+    """Per-sample bin means of every run, for combining batches later."""
+    arrays = {}
+    for r in runs:
+        L = r["L"]
+        for k, v in r["means"].items():
+            arrays[f"L{L}_{k}"] = np.asarray(v)
+        arrays[f"L{L}_temps"] = np.asarray(r["temps"])
+        arrays[f"L{L}_counts"] = np.asarray(r["counts"])
+        arrays[f"L{L}_bins"] = np.asarray(r["bins"])
+        arrays[f"L{L}_meta"] = np.asarray([r["R"], r["steps"], r["measure_every"], r["n_samples"]])
+    np.savez(path, **arrays)
+
+
+def load_runs(paths):
+    """Runs of the same sizes from several saved batches, samples concatenated."""
+    runs = {}
+    for path in paths:
+        z = np.load(path)
+        for L in sorted({int(k.split("_")[0][1:]) for k in z.files}):
+            means = {k: z[f"L{L}_{k}"] for k in ("q2", "qk2", "e")}
+            meta = z[f"L{L}_meta"]
+            if L not in runs:
+                runs[L] = {"L": L, "temps": z[f"L{L}_temps"].tolist(), "R": int(meta[0]), "steps": int(meta[1]),
+                           "measure_every": int(meta[2]), "n_samples": 0, "bins": z[f"L{L}_bins"].tolist(),
+                           "counts": z[f"L{L}_counts"].tolist(), "means": {k: [] for k in means}}
+            r = runs[L]
+            assert np.allclose(r["temps"], z[f"L{L}_temps"]) and r["steps"] == int(meta[1])
+            for k, v in means.items():
+                r["means"][k].append(v)
+            r["n_samples"] += int(meta[3])
+    for r in runs.values():
+        r["means"] = {k: np.concatenate(v, axis=1) for k, v in r["means"].items()}
+    return [runs[L] for L in sorted(runs)]
+
+
+def report(runs, temps, couplings, D):
+    result = {"runs": [{k: r[k] for k in ("L", "n_samples", "steps") if k in r} for r in runs],
+              "temps": list(map(float, temps)), "couplings": couplings, "D": D,
+              "xi_over_L": {str(r["L"]): [v.tolist() for v in xi_over_L(r)] for r in runs},
+              "thermalisation_chi0": {str(r["L"]): thermalisation(r) for r in runs},
+              "crossings": []}
+    for a, b in zip(runs, runs[1:]):
+        try:
+            result["crossings"].append(analyse(a, b))
+        except ValueError as e:
+            result["crossings"].append({"pair": [a["L"], b["L"]], "error": str(e)})
+    return result
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--L", type=int, nargs="+", default=[8, 16])
@@ -144,7 +195,18 @@ def main(argv=None):
     ap.add_argument("--D", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=1309)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None, help="write per-sample bin means (npz)")
+    ap.add_argument("--combine", nargs="+", default=None, help="analyse saved batches together (no GPU)")
     args = ap.parse_args(argv)
+    if args.combine:
+        runs = load_runs(args.combine)
+        result = report(runs, runs[0]["temps"], args.couplings, args.D)
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(json.dumps(result, default=float))
+        print(json.dumps({"samples": [r["n_samples"] for r in runs], "crossings": result["crossings"]},
+                         default=float))
+        return
     import torch
     torch.cuda.set_device(0)
     temps = inputs.geometric_temps(args.temps[0], args.temps[1], int(args.temps[2]))
@@ -154,16 +216,10 @@ def main(argv=None):
         runs.append(simulate(L, args.samples, temps, args.replicas, n, args.measure_every,
                              args.seed + L, args.couplings, args.D,
                              log=lambda msg: print(msg, file=sys.stderr, flush=True)))
-    result = {"runs": [{k: r[k] for k in ("L", "n_samples", "steps", "seconds")} for r in runs],
-              "temps": temps.tolist(), "couplings": args.couplings, "D": args.D,
-              "xi_over_L": {str(r["L"]): [v.tolist() for v in xi_over_L(r)] for r in runs},
-              "thermalisation_chi0": {str(r["L"]): thermalisation(r) for r in runs},
-              "crossings": []}
-    for a, b in zip(runs, runs[1:]):
-        try:
-            result["crossings"].append(analyse(a, b))
-        except ValueError as e:
-            result["crossings"].append({"pair": [a["L"], b["L"]], "error": str(e)})
+    if args.save:
+        save_runs(args.save, runs)
+    result = report(runs, temps, args.couplings, args.D)
+    result["seconds"] = {str(r["L"]): r["seconds"] for r in runs}
     text = json.dumps(result, default=float)
     if args.out:
         with open(args.out, "w") as fh:

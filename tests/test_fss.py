@@ -49,3 +49,30 @@ def test_xi_over_L_and_thermalisation():
     th = fss.thermalisation(r)
     assert th[0]["diff"] == pytest.approx([0.0] * 5)
     assert np.allclose(th[1]["diff"], 0.01 * 10.0)   # the earlier bin was 1 % higher
+
+
+def test_save_and_combine(tmp_path):
+    """Two saved batches of independent samples combine into one run with
+    the samples of both, and the analysis of the combination equals that of
+    the concatenated runs."""
+    T = np.linspace(0.8, 1.2, 12)
+    Tc, yc, s1 = 0.95, 0.6, -0.8
+    s2 = s1 * 2 ** 1.5 / 2
+    batches = []
+    for k in range(2):
+        a = _run(8, T, yc + s1 * (T - Tc), 50, 0.02, 10 + k)
+        b = _run(16, T, yc + s2 * (T - Tc), 50, 0.02, 20 + k)
+        for r in (a, b):
+            r.update(R=2, steps=100, measure_every=10)
+            r["means"] = {key: np.asarray(v) for key, v in r["means"].items()}
+        path = tmp_path / f"b{k}.npz"
+        fss.save_runs(path, [a, b])
+        batches.append((a, b, path))
+    runs = fss.load_runs([str(p) for _, _, p in batches])
+    assert [r["n_samples"] for r in runs] == [100, 100]
+    both = [dict(batches[0][i], n_samples=100,
+                 means={key: np.concatenate([batches[0][i]["means"][key], batches[1][i]["means"][key]], axis=1)
+                        for key in ("q2", "qk2", "e")}) for i in (0, 1)]
+    want = fss.analyse(*both)
+    got = fss.analyse(*runs)
+    assert got["T_cross"] == pytest.approx(want["T_cross"])
