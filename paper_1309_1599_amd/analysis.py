@@ -164,24 +164,41 @@ def tau_int(x, c=6.0):
     return float(tau)
 
 
-def crossing(T, y1, y2, n_fit=4, order=1):
+def crossing(T, y1, y2, n_fit=4, order=1, extrapolate=0.0):
     """Temperature where curves y1(T) and y2(T) cross, from polynomial fits
     of degree `order` to the n_fit temperatures nearest to the crossing
     (Sec. IV: four temperatures, linear fits).  Returns (T_cross, y_cross,
-    slope1, slope2).  Raises ValueError if the curves do not cross in T."""
+    slope1, slope2).  If the curves do not cross inside the grid, the fits
+    to the n_fit temperatures at the end where they come closest may place
+    the crossing up to `extrapolate` times the width of the grid beyond it;
+    otherwise (or farther out) ValueError."""
     T = np.asarray(T, dtype=np.float64)
     d = np.asarray(y1, dtype=np.float64) - np.asarray(y2, dtype=np.float64)
     sign = np.nonzero(np.diff(np.sign(d)) != 0)[0]
+    width = T.max() - T.min()
     if len(sign) == 0:
-        raise ValueError("the curves do not cross in the temperature range")
-    i = sign[0]
-    t0 = T[i] - d[i] * (T[i + 1] - T[i]) / (d[i + 1] - d[i])
+        if extrapolate <= 0.0:
+            raise ValueError("the curves do not cross in the temperature range")
+        end = 0 if abs(d[0]) < abs(d[-1]) else len(T) - 1
+        near = np.sort(np.argsort(np.abs(T - T[end]))[:n_fit])
+        p1 = np.polyfit(T[near], np.asarray(y1)[near], 1)
+        p2 = np.polyfit(T[near], np.asarray(y2)[near], 1)
+        if p1[0] == p2[0]:
+            raise ValueError("the curves do not cross in the temperature range")
+        t0 = (p2[1] - p1[1]) / (p1[0] - p2[0])
+        if not (T.min() - extrapolate * width <= t0 <= T.max() + extrapolate * width):
+            raise ValueError("the curves do not cross near the temperature range")
+    else:
+        i = sign[0]
+        t0 = T[i] - d[i] * (T[i + 1] - T[i]) / (d[i + 1] - d[i])
     near = np.sort(np.argsort(np.abs(T - t0))[:n_fit])
     p1 = np.polyfit(T[near], np.asarray(y1)[near], order)
     p2 = np.polyfit(T[near], np.asarray(y2)[near], order)
     roots = np.roots(np.polysub(p1, p2))
     roots = roots[np.isreal(roots)].real
     lo, hi = T[near].min(), T[near].max()
+    if len(sign) == 0:   # extrapolated: the fit windows end at the grid edge
+        lo, hi = lo - extrapolate * width, hi + extrapolate * width
     inside = roots[(roots >= lo - 1e-12) & (roots <= hi + 1e-12)]
     tc = float(inside[np.argmin(np.abs(inside - t0))]) if len(inside) else float(t0)
     d1, d2 = np.polyder(p1), np.polyder(p2)

@@ -90,8 +90,10 @@ def xi_over_L(run, b=0):
     return A.jackknife(_blocks(run, b), lambda m: A.xi_second_moment(m[0], m[1], L) / L)
 
 
-def analyse(small, large, n_fit=4):
-    """Crossing of xi/L between two runs on one temperature grid."""
+def analyse(small, large, n_fit=4, extrapolate=0.25):
+    """Crossing of xi/L between two runs on one temperature grid (linear
+    fits to the four temperatures nearest to it; a crossing up to a quarter
+    of the grid's width beyond its edge is extrapolated and flagged)."""
     T = np.asarray(small["temps"])
     assert np.allclose(T, large["temps"]), "the two sizes need one temperature grid"
     n = min(small["n_samples"], large["n_samples"])
@@ -101,13 +103,13 @@ def analyse(small, large, n_fit=4):
     def f(m):
         y1 = A.xi_second_moment(m[0], m[1], Ls) / Ls
         y2 = A.xi_second_moment(m[2], m[3], Ll) / Ll
-        tc, yc, s1, s2 = A.crossing(T, y1, y2, n_fit=n_fit)
+        tc, yc, s1, s2 = A.crossing(T, y1, y2, n_fit=n_fit, extrapolate=extrapolate)
         # d xi/dT = L d(xi/L)/dT
         return np.array([tc, yc, (Ll * s2) / (Ls * s1)])
 
     est, err = A.jackknife(np.concatenate([b1, b2], axis=1), f)
     out = {"pair": [Ls, Ll], "T_cross": [est[0], err[0]], "xi_over_L_cross": [est[1], err[1]],
-           "slope_ratio": [est[2], err[2]]}
+           "slope_ratio": [est[2], err[2]], "extrapolated": bool(est[0] < T.min() or est[0] > T.max())}
     if Ll == 2 * Ls and est[2] > 2:
         nu = A.nu_from_slope_ratio(est[2])
         # error of nu from the jackknife of the ratio (propagated)

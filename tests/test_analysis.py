@@ -154,3 +154,17 @@ def test_thermal_means_of_an_oracle_run():
     want = np.asarray(energies).mean(axis=(0, 1)) / L ** 3
     np.testing.assert_allclose(means["e"], want, rtol=1e-12)
     assert Rr.dtype == ptsg.MEAS_DTYPE
+
+
+def test_crossing_extrapolated_just_beyond_the_grid():
+    """Lines meeting slightly below the grid: found with extrapolation
+    allowed, refused without it or when too far out."""
+    T = np.linspace(1.0, 1.4, 9)
+    y1 = 0.6 - 0.8 * (T - 0.95)
+    y2 = 0.6 - 1.2 * (T - 0.95)
+    tc, yc, s1, s2 = A.crossing(T, y1, y2, extrapolate=0.25)
+    assert tc == pytest.approx(0.95) and yc == pytest.approx(0.6)
+    with pytest.raises(ValueError):
+        A.crossing(T, y1, y2)
+    with pytest.raises(ValueError):
+        A.crossing(T, 0.6 - 0.8 * (T - 0.5), 0.6 - 1.2 * (T - 0.5), extrapolate=0.25)
