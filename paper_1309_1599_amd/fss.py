@@ -32,7 +32,7 @@ from . import inputs, ptsg
 
 
 def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimodal", D=1.0,
-             flags=ptsg.PT_F_GRAPHS | ptsg.PT_F_AUTOTUNE, log=print):
+             flags=ptsg.PT_F_GRAPHS | ptsg.PT_F_AUTOTUNE, chiral=False, log=print):
     temps = np.asarray(temps, dtype=np.float64)
     T = len(temps)
     if couplings == "bimodal":
@@ -48,7 +48,9 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
     for i, (lo, hi) in enumerate(bins):
         which[lo:hi] = i
     nb = len(bins)
-    sums = {k: np.zeros((nb, n_samples, T)) for k in ("q2", "qk2", "e")}
+    keys = ("q2", "qk2", "e") + (("cg2", "cgk2") if chiral else ())
+    what = ptsg.PT_M_OVERLAP | (ptsg.PT_M_CHIRAL if chiral else 0)
+    sums = {k: np.zeros((nb, n_samples, T)) for k in keys}
     counts = np.zeros(nb)
     t0 = time.perf_counter()
     m = 0
@@ -56,7 +58,7 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
         ptsg.pt_step(ctx, 1, L)
         ptsg.pt_swap(ctx)
         if step % measure_every == 0:
-            recs = ptsg.pt_measure(ctx, ptsg.PT_M_OVERLAP)
+            recs = ptsg.pt_measure(ctx, what)
             b = which[m]
             if b >= 0:
                 F = A.fields(recs[None], L)
@@ -75,22 +77,27 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
             "means": {k: v.tolist() for k, v in means.items()}, "seconds": time.perf_counter() - t0}
 
 
-def _blocks(run, b=0):
-    """(n_samples, 2, T) per-sample chi(0), chi(k_min) of bin b (0 = last)."""
+CHANNELS = {"sg": ("q2", "qk2"), "cg": ("cg2", "cgk2")}
+
+
+def _blocks(run, b=0, channel="sg"):
+    """(n_samples, 2, T) per-sample chi(0), chi(k_min) of bin b (0 = last)
+    for the spin-glass ("sg") or chiral-glass ("cg") overlap."""
     N = run["L"] ** 3
-    q2 = np.asarray(run["means"]["q2"])[b]
-    qk2 = np.asarray(run["means"]["qk2"])[b]
+    k0, kk = CHANNELS[channel]
+    q2 = np.asarray(run["means"][k0])[b]
+    qk2 = np.asarray(run["means"][kk])[b]
     return np.stack([N * q2, N * qk2], axis=1)
 
 
-def xi_over_L(run, b=0):
+def xi_over_L(run, b=0, channel="sg"):
     """xi/L per temperature from the disorder-averaged susceptibilities of
     bin b, with jackknife errors over samples."""
     L = run["L"]
-    return A.jackknife(_blocks(run, b), lambda m: A.xi_second_moment(m[0], m[1], L) / L)
+    return A.jackknife(_blocks(run, b, channel), lambda m: A.xi_second_moment(m[0], m[1], L) / L)
 
 
-def analyse(small, large, n_fit=4, extrapolate=0.25):
+def analyse(small, large, n_fit=4, extrapolate=0.25, channel="sg"):
     """Crossing of xi/L between two runs on one temperature grid (linear
     fits to the four temperatures nearest to it; a crossing up to a quarter
     of the grid's width beyond its edge is extrapolated and flagged)."""
@@ -98,7 +105,7 @@ def analyse(small, large, n_fit=4, extrapolate=0.25):
     assert np.allclose(T, large["temps"]), "the two sizes need one temperature grid"
     n = min(small["n_samples"], large["n_samples"])
     Ls, Ll = small["L"], large["L"]
-    b1, b2 = _blocks(small)[:n], _blocks(large)[:n]   # sample i of each size forms block i
+    b1, b2 = _blocks(small, 0, channel)[:n], _blocks(large, 0, channel)[:n]   # sample i of each size forms block i
 
     def f(m):
         y1 = A.xi_second_moment(m[0], m[1], Ls) / Ls
@@ -108,7 +115,7 @@ def analyse(small, large, n_fit=4, extrapolate=0.25):
         return np.array([tc, yc, (Ll * s2) / (Ls * s1)])
 
     est, err = A.jackknife(np.concatenate([b1, b2], axis=1), f)
-    out = {"pair": [Ls, Ll], "T_cross": [est[0], err[0]], "xi_over_L_cross": [est[1], err[1]],
+    out = {"channel": channel, "pair": [Ls, Ll], "T_cross": [est[0], err[0]], "xi_over_L_cross": [est[1], err[1]],
            "slope_ratio": [est[2], err[2]], "extrapolated": bool(est[0] < T.min() or est[0] > T.max())}
     if Ll == 2 * Ls and est[2] > 2:
         nu = A.nu_from_slope_ratio(est[2])
@@ -154,7 +161,7 @@ def load_runs(paths):
     for path in paths:
         z = np.load(path)
         for L in sorted({int(k.split("_")[0][1:]) for k in z.files}):
-            means = {k: z[f"L{L}_{k}"] for k in ("q2", "qk2", "e")}
+            means = {k: z[f"L{L}_{k}"] for k in ("q2", "qk2", "e", "cg2", "cgk2") if f"L{L}_{k}" in z.files}
             meta = z[f"L{L}_meta"]
             if L not in runs:
                 runs[L] = {"L": L, "temps": z[f"L{L}_temps"].tolist(), "R": int(meta[0]), "steps": int(meta[1]),
@@ -171,16 +178,20 @@ def load_runs(paths):
 
 
 def report(runs, temps, couplings, D):
+    channels = ["sg"] + (["cg"] if all("cg2" in r["means"] for r in runs) else [])
     result = {"runs": [{k: r[k] for k in ("L", "n_samples", "steps") if k in r} for r in runs],
               "temps": list(map(float, temps)), "couplings": couplings, "D": D,
               "xi_over_L": {str(r["L"]): [v.tolist() for v in xi_over_L(r)] for r in runs},
               "thermalisation_chi0": {str(r["L"]): thermalisation(r) for r in runs},
               "crossings": []}
-    for a, b in zip(runs, runs[1:]):
-        try:
-            result["crossings"].append(analyse(a, b))
-        except ValueError as e:
-            result["crossings"].append({"pair": [a["L"], b["L"]], "error": str(e)})
+    if "cg" in channels:
+        result["xi_cg_over_L"] = {str(r["L"]): [v.tolist() for v in xi_over_L(r, 0, "cg")] for r in runs}
+    for ch in channels:
+        for a, b in zip(runs, runs[1:]):
+            try:
+                result["crossings"].append(analyse(a, b, channel=ch))
+            except ValueError as e:
+                result["crossings"].append({"channel": ch, "pair": [a["L"], b["L"]], "error": str(e)})
     return result
 
 
@@ -196,6 +207,7 @@ def main(argv=None):
     ap.add_argument("--couplings", choices=("bimodal", "gaussian"), default="bimodal")
     ap.add_argument("--D", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=1309)
+    ap.add_argument("--chiral", action="store_true", help="also measure the chiral-glass overlap (Sec. II.B)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write per-sample bin means (npz)")
     ap.add_argument("--combine", nargs="+", default=None, help="analyse saved batches together (no GPU)")
@@ -216,7 +228,7 @@ def main(argv=None):
     runs = []
     for L, n in zip(args.L, steps):
         runs.append(simulate(L, args.samples, temps, args.replicas, n, args.measure_every,
-                             args.seed + L, args.couplings, args.D,
+                             args.seed + L, args.couplings, args.D, chiral=args.chiral,
                              log=lambda msg: print(msg, file=sys.stderr, flush=True)))
     if args.save:
         save_runs(args.save, runs)

@@ -76,3 +76,18 @@ def test_save_and_combine(tmp_path):
     want = fss.analyse(*both)
     got = fss.analyse(*runs)
     assert got["T_cross"] == pytest.approx(want["T_cross"])
+
+
+def test_chiral_channel():
+    """The chiral-glass channel reads cg2 / cgk2 and finds its own crossing."""
+    T = np.linspace(0.8, 1.2, 12)
+    a = _run(8, T, 0.6 - 0.8 * (T - 0.95), 40, 0.0, 1)
+    b = _run(16, T, 0.6 - 1.4 * (T - 0.95), 40, 0.0, 2)
+    ac = _run(8, T, 0.05 - 0.1 * (T - 1.1), 40, 0.0, 3)
+    bc = _run(16, T, 0.05 - 0.2 * (T - 1.1), 40, 0.0, 4)
+    for r, c in ((a, ac), (b, bc)):
+        r["means"]["cg2"] = c["means"]["q2"]
+        r["means"]["cgk2"] = c["means"]["qk2"]
+    assert fss.analyse(a, b)["T_cross"][0] == pytest.approx(0.95)
+    res = fss.analyse(a, b, channel="cg")
+    assert res["channel"] == "cg" and res["T_cross"][0] == pytest.approx(1.1)
