@@ -143,7 +143,12 @@ enum {
      * chains, at least 4, at most 2 GB of spins) and use the fastest; results are cached
      * for the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
      * Runs kernels on the current device, so pt_workspace_size needs the
-     * device too when this flag is set. */
+     * device too when this flag is set.  When the environment variable
+     * PTSG_PLAN_CACHE names a file, results are also looked up there before
+     * timing and appended after it, one text line per (device architecture,
+     * CU count, L, n_temps, n_replicas, samples timed, PT_F_GRAPHS,
+     * PT_F_BIMODAL); lines that do not parse or name a mapping the lattice
+     * cannot use are skipped, and an unwritable file is not an error. */
     PT_F_AUTOTUNE = 32u,
     /* The paper's coupling family (Sec. II.A): every bond is
      * M = J*1 + D_sym, J = +-1, the six entries D_ab (a <= b) of the
@@ -211,6 +216,12 @@ pt_status pt_set_spins(pt_ctx *ctx, int sample, int rep, int tslot, const float 
 
 /* out[k] = index j of the chain now at slot k, for one (sample, replica). */
 pt_status pt_get_perm(pt_ctx *ctx, int sample, int rep, int32_t *out);
+
+/* The same for every (sample, replica) at once, ordered by sample, replica,
+ * slot (sum over samples of n_replicas * n_temps entries, the order of
+ * pt_get_energy): one copy for following the temperature random walk of
+ * every chain (Sec. III).  Synchronous. */
+pt_status pt_get_perms(pt_ctx *ctx, int32_t *out);
 
 /* Energies (Eq. (1)) of all chains, ordered by sample, replica, slot. */
 pt_status pt_get_energy(pt_ctx *ctx, double *out);

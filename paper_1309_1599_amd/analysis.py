@@ -17,10 +17,11 @@ Everything here is plain numpy on the records that `pt_measure` returns
   run, the one before it the second quarter, and so on) and the
   thermalisation test built on it;
 * jackknife errors (Sec. IV) and the integrated autocorrelation time of a
-  series (Sec. III: the temperature random walk);
+  series, or of the temperature random walk of a sample's chains (Sec. III);
 * the crossing temperature of xi_L/L and xi_2L/(2L) from low-order fits to
-  the temperatures nearest to it, and the exponent nu from the ratio of the
-  slopes there (Sec. IV).
+  the temperatures nearest to it, the exponent nu from the ratio of the
+  slopes there and eta from the ratio of the susceptibilities there
+  (Sec. IV, quotient method).
 """
 import numpy as np
 
@@ -147,14 +148,19 @@ def thermalisation(series):
 
 def tau_int(x, c=6.0):
     """Integrated autocorrelation time tau = 1/2 + sum_{t>=1} rho(t) with
-    Sokal's automatic window (the smallest W with W >= c tau(W))."""
+    Sokal's automatic window (the smallest W with W >= c tau(W)).  x is one
+    series (n,) or several series of the same process (n, m), e.g. the
+    temperature indices of all chains of a sample; their autocovariances
+    (each about its own mean) are averaged before normalising."""
     x = np.asarray(x, dtype=np.float64)
-    x = x - x.mean()
-    n = len(x)
+    if x.ndim == 1:
+        x = x[:, None]
+    x = x - x.mean(axis=0)
+    n = x.shape[0]
     if n < 2 or not np.any(x):
         return 0.5
-    f = np.fft.rfft(x, 2 * n)
-    acf = np.fft.irfft(f * np.conj(f))[:n]
+    f = np.fft.rfft(x, 2 * n, axis=0)
+    acf = np.fft.irfft(f * np.conj(f), 2 * n, axis=0)[:n].mean(axis=1)
     rho = acf / acf[0]
     tau = 0.5
     for w in range(1, n):
@@ -162,6 +168,22 @@ def tau_int(x, c=6.0):
         if w >= c * tau:
             break
     return float(tau)
+
+
+def slot_of_chain(perm):
+    """Inverse of a permutation array (..., T): entry j = slot of chain j."""
+    perm = np.asarray(perm)
+    inv = np.empty_like(perm)
+    np.put_along_axis(inv, perm, np.broadcast_to(np.arange(perm.shape[-1]), perm.shape), axis=-1)
+    return inv
+
+
+def temperature_walk_tau(slots):
+    """Sec. III: integrated autocorrelation time of the random walk in
+    temperature of one sample, in units of the sampling interval.
+    slots: (n_times, n_chains) temperature index of every chain of the
+    sample over time (all replicas)."""
+    return tau_int(np.asarray(slots, dtype=np.float64))
 
 
 def crossing(T, y1, y2, n_fit=4, order=1, extrapolate=0.0):
@@ -205,9 +227,23 @@ def crossing(T, y1, y2, n_fit=4, order=1, extrapolate=0.0):
     return tc, float(np.polyval(p1, tc)), float(np.polyval(d1, tc)), float(np.polyval(d2, tc))
 
 
-def nu_from_slope_ratio(ratio):
-    """nu from (d xi_2L/dT)/(d xi_L/dT) = 2^(1 + 1/nu) at the crossing (Sec. IV)."""
-    return 1.0 / (np.log2(ratio) - 1.0)
+def nu_from_slope_ratio(ratio, b=2.0):
+    """nu from (d xi_bL/dT)/(d xi_L/dT) = b^(1 + 1/nu) at the crossing
+    (Sec. IV, quotient method; the paper's pairs have b = 2)."""
+    return 1.0 / (np.log(ratio) / np.log(b) - 1.0)
+
+
+def eta_from_chi_ratio(ratio, b=2.0):
+    """eta from chi_bL / chi_L = b^(2 - eta) at the crossing (Sec. IV)."""
+    return 2.0 - np.log(ratio) / np.log(b)
+
+
+def value_at(T, y, t, n_fit=4):
+    """y at temperature t from a linear fit to the n_fit grid temperatures
+    nearest to t (the fits used at the crossing)."""
+    T = np.asarray(T, dtype=np.float64)
+    near = np.sort(np.argsort(np.abs(T - t))[:n_fit])
+    return float(np.polyval(np.polyfit(T[near], np.asarray(y, dtype=np.float64)[near], 1), t))
 
 
 def crossing_jackknife(T, blocks1, blocks2, n_fit=4, order=1):

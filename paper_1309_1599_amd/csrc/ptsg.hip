@@ -7,8 +7,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <sstream>
 #include <mutex>
 #include <tuple>
 #include <new>
@@ -669,6 +672,64 @@ pt_status check_ctx(pt_ctx *c)
     return PT_OK;
 }
 
+// Plan cache on disk.  The file that PTSG_PLAN_CACHE names holds one tuned
+// mapping per line:
+//   ptsg-plan <version> <arch> <CUs> <L> <n_temps> <n_replicas> <samples timed>
+//             <graphs 0|1> <bimodal 0|1> <site|chain|resident>
+// Lines that do not parse, carry another version, or name a mapping the
+// lattice cannot use are skipped; the last matching line wins.  The version
+// changes whenever the kernels change enough to move the choice.
+constexpr int kPlanVersion = 1;
+
+struct PlanKey {
+    std::string arch;
+    int cus = 0, L = 0, T = 0, R = 0, n = 0, graphs = 0, bimodal = 0;
+    std::string text() const
+    {
+        std::ostringstream o;
+        o << "ptsg-plan " << kPlanVersion << ' ' << arch << ' ' << cus << ' ' << L << ' ' << T << ' ' << R << ' '
+          << n << ' ' << graphs << ' ' << bimodal;
+        return o.str();
+    }
+};
+
+const char *const kMappingName[3] = {"site", "chain", "resident"};
+
+bool mapping_fits(int m, int L)
+{
+    return m == kSiteLanes || (m == kChainLanes && L <= 128) || (m == kResident && L <= kRsMaxL);
+}
+
+int plan_cache_lookup(const PlanKey &k)
+{
+    const char *path = std::getenv("PTSG_PLAN_CACHE");
+    if (!path || !*path) return -1;
+    std::ifstream in(path);
+    const std::string want = k.text() + ' ';
+    std::string line;
+    int found = -1;
+    while (std::getline(in, line)) {
+        if (line.compare(0, want.size(), want) != 0) continue;
+        const std::string name = line.substr(want.size());
+        for (int m = 0; m < 3; ++m)
+            if (name == kMappingName[m] && mapping_fits(m, k.L)) found = m;
+    }
+    return found;
+}
+
+// Appends one line; a file that cannot be written leaves the tuning result
+// in the process cache only.
+void plan_cache_store(const PlanKey &k, int m)
+{
+    const char *path = std::getenv("PTSG_PLAN_CACHE");
+    if (!path || !*path) return;
+    const std::string line = k.text() + ' ' + kMappingName[m] + '\n';
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fwrite(line.data(), 1, line.size(), f);
+        std::fclose(f);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -939,15 +1000,22 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
 // on a temporary context holding a representative share of those samples
 // (enough for 4096 chains, at least 4, at most 2 GB of spins; best of two,
 // after a warm-up step), and keep the fastest.  The step is long enough for
-// the chain-lane order to pay for its first, cold pass through the cache.  Results are cached per (device, L, n_temps, n_replicas,
-// samples timed, graphs) for the process.
+// the chain-lane order to pay for its first, cold pass through the cache.
+// Bimodal samples are timed in their byte coding.  Results are cached per
+// (device, L, n_temps, n_replicas, samples timed, graphs, bimodal) for the
+// process, and in the file PTSG_PLAN_CACHE names when it is set.
 static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &mapping)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, bool>, int> cache;
+    static std::map<std::tuple<int, int, int, int, int, bool, bool>, int> cache;
     const unsigned graphs = d->flags & PT_F_GRAPHS;
+    const unsigned bimodal = d->flags & PT_F_BIMODAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return fail(PT_EDEVICE, "no HIP device");
+    hipDeviceProp_t prop{};
+    PT_HIP(hipGetDeviceProperties(&prop, dev));
+    std::string arch(prop.gcnArchName);
+    std::replace(arch.begin(), arch.end(), ' ', '_');
     mapping.assign(d->n_samples, kSiteLanes);
     std::map<std::pair<int, int>, std::vector<int>> classes;
     for (int s = 0; s < d->n_samples; ++s) classes[{d->L[s], d->n_temps[s]}].push_back(s);
@@ -960,12 +1028,15 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
         int n = static_cast<int>(std::max<int64_t>(4, (4096 + C - 1) / C));
         while (n > 1 && n * C * chain_bytes > (2ll << 30)) --n;
         n = std::min<int>(n, static_cast<int>(cl.second.size()));
-        const auto key = std::make_tuple(dev, L, cl.first.second, d->n_replicas, n, graphs != 0);
+        const auto key = std::make_tuple(dev, L, cl.first.second, d->n_replicas, n, graphs != 0, bimodal != 0);
+        const PlanKey pkey{arch, prop.multiProcessorCount, L, cl.first.second, d->n_replicas, n,
+                           graphs != 0, bimodal != 0};
         int best = L > 128 ? kSiteLanes : -1;  // the only mapping beyond L = 128
         {
             std::lock_guard<std::mutex> lock(mu);
             auto it = cache.find(key);
             if (it != cache.end()) best = it->second;
+            if (best < 0 && (best = plan_cache_lookup(pkey)) >= 0) cache[key] = best;
         }
         if (best < 0) {
             std::vector<int> Ls(n, L), Ts(n, cl.first.second);
@@ -988,7 +1059,7 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
                 t.couplings = cpl.data();
                 t.n_replicas = d->n_replicas;
                 t.seed = d->seed;
-                t.flags = cand.second | graphs;
+                t.flags = cand.second | graphs | bimodal;
                 pt_ctx *tc = nullptr;
                 pt_status st = init_batch(&tc, &t, nullptr);
                 if (st != PT_OK) return st;
@@ -1020,6 +1091,7 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
             }
             std::lock_guard<std::mutex> lock(mu);
             cache[key] = best;
+            plan_cache_store(pkey, best);
         }
         for (int s : cl.second) mapping[s] = best;
     }
@@ -1262,6 +1334,22 @@ pt_status pt_get_perm(pt_ctx *c, int sample, int rep, int32_t *out)
     PT_HIP(hipMemcpyAsync(out, c->perm + P.perm_base[sample] + rep * P.T[sample], sizeof(int) * P.T[sample],
                           hipMemcpyDeviceToHost, c->stream));
     PT_HIP(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+pt_status pt_get_perms(pt_ctx *c, int32_t *out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (!out) return fail(PT_EINVAL, "output is NULL");
+    const Plan &P = c->plan;
+    std::vector<int> perm(P.total_perm);
+    PT_HIP(hipMemcpyAsync(perm.data(), c->perm, perm.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    PT_HIP(hipStreamSynchronize(c->stream));
+    size_t o = 0;
+    for (int s = 0; s < P.S; ++s)
+        for (int r = 0; r < P.R; ++r)
+            for (int k = 0; k < P.T[s]; ++k) out[o++] = perm[P.perm_base[s] + r * P.T[s] + k];
     return PT_OK;
 }
 

@@ -52,6 +52,7 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
     what = ptsg.PT_M_OVERLAP | (ptsg.PT_M_CHIRAL if chiral else 0)
     sums = {k: np.zeros((nb, n_samples, T)) for k in keys}
     counts = np.zeros(nb)
+    walk = np.empty((n_meas, n_samples, R * T), np.int16)   # slot of every chain at each measurement
     t0 = time.perf_counter()
     m = 0
     for step in range(1, steps + 1):
@@ -59,6 +60,7 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
         ptsg.pt_swap(ctx)
         if step % measure_every == 0:
             recs = ptsg.pt_measure(ctx, what)
+            walk[m] = A.slot_of_chain(np.stack(ptsg.pt_get_perms(ctx))).reshape(n_samples, R * T)
             b = which[m]
             if b >= 0:
                 F = A.fields(recs[None], L)
@@ -72,9 +74,13 @@ def simulate(L, n_samples, temps, R, steps, measure_every, seed, couplings="bimo
     pairs = R * (R - 1) // 2
     ptsg.pt_free(ctx)
     means = {k: v / (counts[:, None, None] * pairs) for k, v in sums.items()}
+    # Sec. III: autocorrelation time of each sample's temperature walk over
+    # the last half of the run, in Monte Carlo steps
+    tau = [A.temperature_walk_tau(walk[n_meas // 2:, s]) * measure_every for s in range(n_samples)]
     return {"L": L, "temps": temps.tolist(), "R": R, "steps": steps, "measure_every": measure_every,
             "n_samples": n_samples, "bins": bins, "counts": counts.tolist(),
-            "means": {k: v.tolist() for k, v in means.items()}, "seconds": time.perf_counter() - t0}
+            "means": {k: v.tolist() for k, v in means.items()}, "tau_walk": tau,
+            "seconds": time.perf_counter() - t0}
 
 
 CHANNELS = {"sg": ("q2", "qk2"), "cg": ("cg2", "cgk2")}
@@ -107,20 +113,26 @@ def analyse(small, large, n_fit=4, extrapolate=0.25, channel="sg"):
     Ls, Ll = small["L"], large["L"]
     b1, b2 = _blocks(small, 0, channel)[:n], _blocks(large, 0, channel)[:n]   # sample i of each size forms block i
 
+    b = Ll / Ls
+
     def f(m):
         y1 = A.xi_second_moment(m[0], m[1], Ls) / Ls
         y2 = A.xi_second_moment(m[2], m[3], Ll) / Ll
         tc, yc, s1, s2 = A.crossing(T, y1, y2, n_fit=n_fit, extrapolate=extrapolate)
-        # d xi/dT = L d(xi/L)/dT
-        return np.array([tc, yc, (Ll * s2) / (Ls * s1)])
+        # quotients at the crossing (Sec. IV): d xi/dT = L d(xi/L)/dT, and chi(0)
+        # of both sizes from the same local linear fits
+        ratio_chi = A.value_at(T, m[2], tc, n_fit) / A.value_at(T, m[0], tc, n_fit)
+        return np.array([tc, yc, (Ll * s2) / (Ls * s1), A.eta_from_chi_ratio(ratio_chi, b)])
 
     est, err = A.jackknife(np.concatenate([b1, b2], axis=1), f)
     out = {"channel": channel, "pair": [Ls, Ll], "T_cross": [est[0], err[0]], "xi_over_L_cross": [est[1], err[1]],
-           "slope_ratio": [est[2], err[2]], "extrapolated": bool(est[0] < T.min() or est[0] > T.max())}
-    if Ll == 2 * Ls and est[2] > 2:
-        nu = A.nu_from_slope_ratio(est[2])
+           "slope_ratio": [est[2], err[2]], "eta": [est[3], err[3]],
+           "extrapolated": bool(est[0] < T.min() or est[0] > T.max())}
+    if est[2] > b:
+        nu = A.nu_from_slope_ratio(est[2], b)
         # error of nu from the jackknife of the ratio (propagated)
-        dnu = err[2] / (est[2] * np.log(2) * (np.log2(est[2]) - 1) ** 2)
+        lr = np.log(est[2]) / np.log(b)
+        dnu = err[2] / (est[2] * np.log(b) * (lr - 1) ** 2)
         out["nu"] = [nu, dnu]
     return out
 
@@ -152,6 +164,8 @@ def save_runs(path, runs):
         arrays[f"L{L}_counts"] = np.asarray(r["counts"])
         arrays[f"L{L}_bins"] = np.asarray(r["bins"])
         arrays[f"L{L}_meta"] = np.asarray([r["R"], r["steps"], r["measure_every"], r["n_samples"]])
+        if "tau_walk" in r:
+            arrays[f"L{L}_tau_walk"] = np.asarray(r["tau_walk"])
     np.savez(path, **arrays)
 
 
@@ -171,10 +185,22 @@ def load_runs(paths):
             assert np.allclose(r["temps"], z[f"L{L}_temps"]) and r["steps"] == int(meta[1])
             for k, v in means.items():
                 r["means"][k].append(v)
+            r.setdefault("tau_parts", []).append(z[f"L{L}_tau_walk"] if f"L{L}_tau_walk" in z.files else None)
             r["n_samples"] += int(meta[3])
     for r in runs.values():
         r["means"] = {k: np.concatenate(v, axis=1) for k, v in r["means"].items()}
+        parts = r.pop("tau_parts")
+        if all(t is not None for t in parts):
+            r["tau_walk"] = np.concatenate(parts).tolist()
     return [runs[L] for L in sorted(runs)]
+
+
+def walk_summary(run):
+    """Sec. III criterion: the temperature-walk autocorrelation times of the
+    samples (MCS) and the share of samples whose run is at least 10 of them."""
+    tau = np.asarray(run["tau_walk"], dtype=np.float64)
+    return {"median": float(np.median(tau)), "max": float(tau.max()),
+            "runs_longer_than_10_tau": float(np.mean(run["steps"] >= 10 * tau))}
 
 
 def report(runs, temps, couplings, D):
@@ -183,6 +209,7 @@ def report(runs, temps, couplings, D):
               "temps": list(map(float, temps)), "couplings": couplings, "D": D,
               "xi_over_L": {str(r["L"]): [v.tolist() for v in xi_over_L(r)] for r in runs},
               "thermalisation_chi0": {str(r["L"]): thermalisation(r) for r in runs},
+              "temperature_walk": {str(r["L"]): walk_summary(r) for r in runs if "tau_walk" in r},
               "crossings": []}
     if "cg" in channels:
         result["xi_cg_over_L"] = {str(r["L"]): [v.tolist() for v in xi_over_L(r, 0, "cg")] for r in runs}

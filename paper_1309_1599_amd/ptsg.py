@@ -32,7 +32,7 @@ assert MEAS_DTYPE.itemsize == 744
 
 # Every symbol the C ABI exports (include/ptsg.h).
 EXPORTS = ["pt_init", "pt_workspace_size", "pt_init_batch", "pt_step", "pt_swap", "pt_measure",
-           "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_energy", "pt_get_counters",
+           "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_perms", "pt_get_energy", "pt_get_counters",
            "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping",
            "pt_save", "pt_load", "pt_free", "pt_last_error"]
 
@@ -80,6 +80,7 @@ def load_library(path=LIB_PATH):
         "pt_get_spins": (i, [vp, i, i, i, C.POINTER(C.c_float)]),
         "pt_set_spins": (i, [vp, i, i, i, C.POINTER(C.c_float)]),
         "pt_get_perm": (i, [vp, i, i, C.POINTER(C.c_int32)]),
+        "pt_get_perms": (i, [vp, C.POINTER(C.c_int32)]),
         "pt_get_energy": (i, [vp, C.POINTER(C.c_double)]),
         "pt_get_counters": (i, [vp, C.POINTER(u64), C.POINTER(u64)]),
         "pt_set_stream": (i, [vp, vp]),
@@ -233,6 +234,18 @@ def pt_get_perm(ctx, sample, rep):
     _check(load_library().pt_get_perm(ctx.ptr, sample, rep,
                                       out.ctypes.data_as(C.POINTER(C.c_int32))))
     return out
+
+
+def pt_get_perms(ctx):
+    """Permutations of every (sample, replica): list of [R][T] int32 arrays,
+    entry [r][k] = chain at slot k."""
+    out = np.empty(ctx.n_chains, dtype=np.int32)
+    _check(load_library().pt_get_perms(ctx.ptr, out.ctypes.data_as(C.POINTER(C.c_int32))))
+    res, o = [], 0
+    for T in ctx.n_temps:
+        res.append(out[o:o + ctx.n_replicas * T].reshape(ctx.n_replicas, T))
+        o += ctx.n_replicas * T
+    return res
 
 
 def pt_get_energy(ctx):

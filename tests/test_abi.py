@@ -83,6 +83,7 @@ def test_non_finite_coupling_rejected(lib):
 def test_null_context_is_state_error(lib):
     assert lib.pt_step(None, 1, 1) == ptsg.PT_ESTATE
     assert lib.pt_swap(None) == ptsg.PT_ESTATE
+    assert lib.pt_get_perms(None, None) == ptsg.PT_ESTATE
     assert "pt_init" in ptsg.pt_last_error()
     lib.pt_free(None)  # no-op
 

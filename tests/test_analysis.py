@@ -168,3 +168,28 @@ def test_crossing_extrapolated_just_beyond_the_grid():
         A.crossing(T, y1, y2)
     with pytest.raises(ValueError):
         A.crossing(T, 0.6 - 0.8 * (T - 0.5), 0.6 - 1.2 * (T - 0.5), extrapolate=0.25)
+
+
+def test_temperature_walk_tau_two_state():
+    """Two temperatures, one replica: the two chains sit in opposite slots and
+    trade places with probability p per step.  Each slot series is a two-state
+    Markov chain with rho(t) = (1 - 2p)^t, so tau = (1 - p) / (2p)."""
+    rng = np.random.default_rng(21)
+    for p in (0.5, 0.1):
+        n = 400000
+        flips = rng.random(n) < p
+        perm = np.zeros((n, 2), dtype=np.int32)
+        perm[:, 0] = np.cumsum(flips) % 2            # chain at slot 0
+        perm[:, 1] = 1 - perm[:, 0]
+        slots = A.slot_of_chain(perm)
+        np.testing.assert_array_equal(np.take_along_axis(slots, perm, axis=1), np.tile([0, 1], (n, 1)))
+        assert A.temperature_walk_tau(slots) == pytest.approx((1 - p) / (2 * p), rel=0.05)
+
+
+def test_slot_of_chain_inverts():
+    rng = np.random.default_rng(5)
+    perm = np.stack([rng.permutation(9) for _ in range(6)]).reshape(2, 3, 9)
+    inv = A.slot_of_chain(perm)
+    for idx in np.ndindex(2, 3):
+        for k in range(9):
+            assert inv[idx][perm[idx][k]] == k

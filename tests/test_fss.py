@@ -6,13 +6,13 @@ import pytest
 from paper_1309_1599_amd import fss
 
 
-def _run(L, T, xi_over_L, n_samples, noise, seed):
+def _run(L, T, xi_over_L, n_samples, noise, seed, chi=10.0):
     """A run dict whose per-sample susceptibilities give xi/L = xi_over_L(T)
-    in the disorder average (lattice Ornstein-Zernike form), with
-    multiplicative sample noise."""
+    and chi(0) = chi(T) in the disorder average (lattice Ornstein-Zernike
+    form), with multiplicative sample noise."""
     rng = np.random.default_rng(seed)
     N = L ** 3
-    chi0 = 10.0 * (1 + noise * rng.normal(size=(n_samples, len(T))))
+    chi0 = chi * (1 + noise * rng.normal(size=(n_samples, len(T))))
     xi = xi_over_L * L
     chik = chi0 / (1 + 4 * xi ** 2 * np.sin(np.pi / L) ** 2)
     q2 = np.stack([chi0 / N, chi0 / N * 1.01])          # last bin, then an earlier one
@@ -63,7 +63,7 @@ def test_save_and_combine(tmp_path):
         a = _run(8, T, yc + s1 * (T - Tc), 50, 0.02, 10 + k)
         b = _run(16, T, yc + s2 * (T - Tc), 50, 0.02, 20 + k)
         for r in (a, b):
-            r.update(R=2, steps=100, measure_every=10)
+            r.update(R=2, steps=100, measure_every=10, tau_walk=list(np.arange(50) * 0.5 + k))
             r["means"] = {key: np.asarray(v) for key, v in r["means"].items()}
         path = tmp_path / f"b{k}.npz"
         fss.save_runs(path, [a, b])
@@ -76,6 +76,12 @@ def test_save_and_combine(tmp_path):
     want = fss.analyse(*both)
     got = fss.analyse(*runs)
     assert got["T_cross"] == pytest.approx(want["T_cross"])
+    # temperature-walk times travel with their samples: 0 .. 24.5 and 1 .. 25.5
+    tau = np.concatenate([np.arange(50) * 0.5, np.arange(50) * 0.5 + 1])
+    np.testing.assert_array_equal(runs[0]["tau_walk"], tau)
+    w = fss.walk_summary(runs[0])
+    assert w["max"] == 25.5 and w["median"] == pytest.approx(np.median(tau))
+    assert w["runs_longer_than_10_tau"] == pytest.approx(np.mean(100 >= 10 * tau))
 
 
 def test_chiral_channel():
@@ -91,3 +97,20 @@ def test_chiral_channel():
     assert fss.analyse(a, b)["T_cross"][0] == pytest.approx(0.95)
     res = fss.analyse(a, b, channel="cg")
     assert res["channel"] == "cg" and res["T_cross"][0] == pytest.approx(1.1)
+
+
+@pytest.mark.parametrize("Ls,Ll", [(8, 16), (8, 12)])
+def test_eta_and_nu_from_quotients(Ls, Ll):
+    """chi_bL / chi_L = b^(2 - eta) and (d xi_bL/dT)/(d xi_L/dT) = b^(1 + 1/nu)
+    at the crossing (Sec. IV), for the paper's b = 2 and for b = 3/2."""
+    T = np.linspace(0.8, 1.2, 12)
+    Tc, yc, nu, eta, s1 = 0.95, 0.6, 2.3, -0.4, -0.8
+    b = Ll / Ls
+    s2 = s1 * b ** (1 + 1 / nu) / b
+    chi = 10.0 - 6.0 * (T - Tc)                        # linear: the local fits are exact
+    a = _run(Ls, T, yc + s1 * (T - Tc), 32, 0.0, 1, chi=chi)
+    c = _run(Ll, T, yc + s2 * (T - Tc), 32, 0.0, 2, chi=chi * b ** (2 - eta))
+    res = fss.analyse(a, c)
+    assert res["T_cross"][0] == pytest.approx(Tc, abs=1e-9)
+    assert res["nu"][0] == pytest.approx(nu, rel=1e-6)
+    assert res["eta"][0] == pytest.approx(eta, abs=1e-9)

@@ -83,3 +83,25 @@ def test_smallest_lattice_all_mappings_agree():
         for a, b in zip(out["site"][1], out[other][1]):
             np.testing.assert_array_equal(a, b)
         np.testing.assert_allclose(out["site"][2], out[other][2], rtol=1e-12, atol=1e-12)
+
+
+def test_all_perms_in_one_call():
+    """pt_get_perms returns what pt_get_perm gives per (sample, replica),
+    on a batch whose samples differ in L and in the number of temperatures."""
+    Ls, Ts, R, seed = [8, 12, 8], [5, 9, 3], 3, 407
+    M = [inputs.gaussian_couplings(L, seed, s) for s, L in enumerate(Ls)]
+    temps = [inputs.geometric_temps(0.6, 1.8, T) for T in Ts]
+    ctx = ptsg.pt_init_batch(Ls, M, temps, R, seed)
+    for _ in range(6):
+        ptsg.pt_step(ctx, 1, 2)
+        ptsg.pt_swap(ctx)
+    allp = ptsg.pt_get_perms(ctx)
+    moved = 0
+    for s, T in enumerate(Ts):
+        assert allp[s].shape == (R, T)
+        for r in range(R):
+            np.testing.assert_array_equal(allp[s][r], ptsg.pt_get_perm(ctx, s, r))
+            assert sorted(allp[s][r].tolist()) == list(range(T))
+            moved += int(np.any(allp[s][r] != np.arange(T)))
+    assert moved > 0
+    ptsg.pt_free(ctx)
