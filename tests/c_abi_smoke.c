@@ -2,7 +2,8 @@
  * L = 8, heat-bath + overrelaxation steps, tempering, a measurement, and
  * checks that need nothing but the header -- unit spins, the energy of the
  * returned spins recomputed here from Eq. (1) against pt_get_energy, a
- * permutation of the slots, a checkpoint restored into a fresh context.
+ * permutation of the slots (per replica and all at once), a checkpoint
+ * restored into a fresh context.
  * Prints "ok" and exits 0 on success. */
 #include <math.h>
 #include <stdio.h>
@@ -72,9 +73,13 @@ int main(void)
     double E[6];
     CHECK(pt_get_energy(ctx, E));
     float *s = malloc(sizeof(float) * 3 * N);
+    int all[6];
+    CHECK(pt_get_perms(ctx, all));
     for (int r = 0; r < R; ++r) {
         int perm[3], seen[3] = {0, 0, 0};
         CHECK(pt_get_perm(ctx, 0, r, perm));
+        for (int k = 0; k < T; ++k)
+            if (all[r * T + k] != perm[k]) { fprintf(stderr, "pt_get_perms differs\n"); return 1; }
         for (int k = 0; k < T; ++k) {
             if (perm[k] < 0 || perm[k] >= T || seen[perm[k]]++) { fprintf(stderr, "bad permutation\n"); return 1; }
             CHECK(pt_get_spins(ctx, 0, r, k, s));
