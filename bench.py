@@ -45,7 +45,8 @@ def kernel_hash():
 def pmc_traffic(preset, mapping, expected_hash):
     """HBM bytes per overrelaxation launch from the committed rocprofv3 --pmc
     summary of this preset, if it was taken on the current kernel source with
-    the same mapping."""
+    the same mapping.  The summaries cover Gaussian couplings and the
+    checkerboard order; other variants report null."""
     try:
         text = open(PMC_SUMMARY.format(preset=preset)).read()
     except OSError:
@@ -232,7 +233,7 @@ def main():
                                            "cl_half_sweep_kernel<overrelax>" if mapping == "chain"
                                            else "half_sweep_kernel<overrelax>"),
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": pmc_traffic(args.preset, mapping, kernel_hash()),
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": (None if rows or bimodal else pmc_traffic(args.preset, mapping, kernel_hash())),
                 "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
                 "bytes_per_su": round(bytes_per_su, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
                 "launches": n_l}
