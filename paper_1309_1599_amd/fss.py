@@ -6,15 +6,19 @@ L overrelaxation sweeps + 1 tempering pass) for a number of steps, and a
 measurement every few steps.  Per (sample, temperature slot) it keeps, for
 every logarithmic bin of the measurement series (the last half, the
 quarter before it, ...), the sums of q^2 and |q(k_min)|^2 of the scalar
-spin-glass overlap over the measurements and replica pairs of the bin.
+spin-glass overlap (and, with chiral=True, of the chiral-glass overlap
+averaged over mu) over the measurements and replica pairs of the bin, and
+per sample the autocorrelation time of the temperature random walk of its
+chains (Sec. III).
 
-`analyse` turns two such runs (L and 2L on one temperature grid) into
-xi_L/L and xi_2L/(2L) from the last bin, with jackknife errors over samples
-(the correlation length is computed from the disorder-averaged
-susceptibilities, Sec. II.B), their crossing temperature from linear fits
-to the four temperatures nearest to it, xi/L at the crossing, nu from the
-ratio of the slopes of xi (Sec. IV), and the thermalisation test of
-Sec. III on chi(0) per bin.
+`analyse` turns two such runs (L and bL on one temperature grid, b = 2 in
+the paper) into xi_L/L and xi_bL/(bL) of either channel from the last bin,
+with jackknife errors over samples (the correlation length is computed from
+the disorder-averaged susceptibilities, Sec. II.B): their crossing
+temperature from linear fits to the four temperatures nearest to it, xi/L
+there, nu from the ratio of the slopes of xi and eta from the ratio of the
+susceptibilities (the quotient method of Sec. IV).  `report` adds the
+thermalisation test of Sec. III on chi(0) per bin and the walk times.
 
 Run as  python -m paper_1309_1599_amd.fss --L 8 16 --samples 256 ...
 (--save FILE.npz keeps the per-sample bin means; --combine A.npz B.npz ...
