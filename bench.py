@@ -104,10 +104,11 @@ def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
         "cores": workers,
         "kind": "oracle",
         "single_thread_value": round(single * 1e12, 1),
-        "sample": f"chains of sample 0 at L={L}, each 1 heat-bath + {n_or} overrelaxation sweeps and "
-                  f"one energy, composed to the {n_hb} HB + {n_or_step} OR step: {n_mt} chains on "
-                  f"{workers} threads ({wall:.1f} s wall, {busy:.1f} thread-s); single-threaded "
-                  f"{n_chains} chains ({busy1:.1f} s)",
+        "sample": f"chains on the couplings of sample 0 at L={L} (its temperatures, replica index "
+                  f"running on past the workload's where more chains are needed), each 1 heat-bath + "
+                  f"{n_or} overrelaxation sweeps and one energy, composed to the {n_hb} HB + "
+                  f"{n_or_step} OR step: {n_mt} chains on {workers} threads ({wall:.1f} s wall, "
+                  f"{busy:.1f} thread-s); single-threaded {n_chains} chains ({busy1:.1f} s)",
     }
 
 
