@@ -114,3 +114,27 @@ def test_eta_and_nu_from_quotients(Ls, Ll):
     assert res["T_cross"][0] == pytest.approx(Tc, abs=1e-9)
     assert res["nu"][0] == pytest.approx(nu, rel=1e-6)
     assert res["eta"][0] == pytest.approx(eta, abs=1e-9)
+
+
+def test_combine_from_the_command_line(tmp_path):
+    """--combine analyses saved batches without a GPU and writes the report."""
+    import json
+    import os
+    import subprocess
+    import sys
+    T = np.linspace(0.8, 1.2, 12)
+    a = _run(8, T, 0.6 - 0.8 * (T - 0.95), 40, 0.01, 31)
+    b = _run(16, T, 0.6 - 1.4 * (T - 0.95), 40, 0.01, 32)
+    for r in (a, b):
+        r.update(R=2, steps=100, measure_every=10, tau_walk=[3.0] * 40)
+        r["means"] = {k: np.asarray(v) for k, v in r["means"].items()}
+    fss.save_runs(tmp_path / "x.npz", [a, b])
+    out = subprocess.run([sys.executable, "-m", "paper_1309_1599_amd.fss", "--combine", str(tmp_path / "x.npz"),
+                          "--out", str(tmp_path / "x.json")], capture_output=True, text=True, timeout=120,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert out.returncode == 0, out.stderr
+    line = json.loads(out.stdout)
+    assert line["samples"] == [40, 40] and line["crossings"][0]["channel"] == "sg"
+    rep = json.loads((tmp_path / "x.json").read_text())
+    assert rep["crossings"][0]["T_cross"][0] == pytest.approx(0.95, abs=0.02)
+    assert rep["temperature_walk"]["16"]["runs_longer_than_10_tau"] == 1.0
