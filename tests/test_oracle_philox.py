@@ -83,3 +83,42 @@ def test_philox_uniformity(orc):
     exp = len(u) / 20
     chi2 = ((hist - exp) ** 2 / exp).sum()
     assert chi2 < 45.3  # p ~ 0.001 for 19 dof
+
+
+def _chi2_p(counts):
+    from scipy.stats import chi2
+    counts = np.asarray(counts, dtype=np.float64).ravel()
+    exp = counts.sum() / counts.size
+    return chi2.sf(((counts - exp) ** 2 / exp).sum(), counts.size - 1)
+
+
+def test_philox_streams_horizontal_and_vertical(orc):
+    """A small battery in the spirit of appendix A.4, on the streams the
+    kernels actually draw: across sites at one sweep (the "horizontal"
+    order, one draw per thread), across heat-bath sweeps at one site, across
+    replicas and across samples.  For each: every byte of every word is
+    flat, pairs of consecutive 23-bit uniforms are flat on a 16 x 16 grid,
+    and consecutive uniforms are uncorrelated."""
+    n = 1 << 14
+    key = [0x13091599, 0x2013]
+    streams = {
+        "sites": [[i, 5, 0, orc.ctr3(0, 3, 1)] for i in range(n)],
+        "sweeps": [[77, s, 0, orc.ctr3(0, 3, 1)] for s in range(n)],
+        "replicas x slots": [[77, 5, 0, orc.ctr3(0, k, r)] for r in range(64) for k in range(n // 64)],
+        "samples": [[77, 5, m, orc.ctr3(0, 3, 1)] for m in range(n)],
+    }
+    for name, ctrs in streams.items():
+        w = np.array([orc.philox(key, c) for c in ctrs], dtype=np.uint32)        # (n, 4)
+        for j in range(4):
+            for b in range(4):
+                byte = (w[:, j] >> np.uint32(8 * b)) & np.uint32(0xFF)
+                assert _chi2_p(np.bincount(byte, minlength=256)) > 1e-4, (name, j, b)
+        u = (w[:, 0] >> np.uint32(9)).astype(np.float64) / 2 ** 23
+        pairs = np.histogram2d(u[:-1], u[1:], bins=16, range=[[0, 1], [0, 1]])[0]
+        assert _chi2_p(pairs) > 1e-4, name
+        r = np.corrcoef(u[:-1], u[1:])[0, 1]
+        assert abs(r) < 4 / np.sqrt(n), (name, r)
+        # the two words one heat-bath update uses are independent of each other
+        u1 = (w[:, 1] >> np.uint32(9)).astype(np.float64) / 2 ** 23
+        assert abs(np.corrcoef(u, u1)[0, 1]) < 4 / np.sqrt(n), name
+        assert _chi2_p(np.histogram2d(u, u1, bins=16, range=[[0, 1], [0, 1]])[0]) > 1e-4, name
