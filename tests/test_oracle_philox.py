@@ -94,7 +94,7 @@ def _chi2_p(counts):
 
 def test_philox_streams_horizontal_and_vertical(orc):
     """A small battery in the spirit of appendix A.4, on the streams the
-    kernels actually draw: across sites at one sweep (the "horizontal"
+    kernels actually draw: across sites at one sweep (the horizontal
     order, one draw per thread), across heat-bath sweeps at one site, across
     replicas and across samples.  For each: every byte of every word is
     flat, pairs of consecutive 23-bit uniforms are flat on a 16 x 16 grid,
