@@ -138,3 +138,59 @@ def test_combine_from_the_command_line(tmp_path):
     rep = json.loads((tmp_path / "x.json").read_text())
     assert rep["crossings"][0]["T_cross"][0] == pytest.approx(0.95, abs=0.02)
     assert rep["temperature_walk"]["16"]["runs_longer_than_10_tau"] == 1.0
+
+
+def test_simulate_host_logic_with_a_scripted_library(monkeypatch):
+    """fss.simulate's bookkeeping on the CPU: the library calls are replaced
+    by a scripted stand-in whose records carry known overlaps, so the bin
+    means, counts and walk times can be checked exactly."""
+    from paper_1309_1599_amd import ptsg
+    L, S, R, steps, every = 4, 3, 2, 64, 2
+    temps = np.linspace(1.0, 2.0, 5)
+    T, N = len(temps), L ** 3
+    state = {"m": 0}
+    rng = np.random.default_rng(9)
+
+    def q_of(s, k, m):
+        return 0.1 * (s + 1) + 0.01 * k + 0.001 * m
+
+    def init(Ls, cpl, ts, n_rep, seed, flags=0):
+        assert Ls == [L] * S and n_rep == R and len(cpl) == S and flags & ptsg.PT_F_BIMODAL
+        state["perm"] = np.stack([np.stack([np.arange(T)] * R)] * S)
+        return "ctx"
+
+    def swap(ctx):
+        state["perm"] = np.stack([np.stack([rng.permutation(T) for _ in range(R)]) for _ in range(S)])
+
+    def measure(ctx, what):
+        assert what & ptsg.PT_M_OVERLAP and what & ptsg.PT_M_CHIRAL
+        out = np.zeros(S * T, ptsg.MEAS_DTYPE)
+        for i, (s, k) in enumerate((s, k) for s in range(S) for k in range(T)):
+            out[i]["sample"], out[i]["tslot"], out[i]["rep_b"] = s, k, 1
+            out[i]["q0"][0] = q_of(s, k, state["m"])
+            out[i]["qk_re"][:, 0] = 0.2
+            out[i]["cg0"] = 0.05 * (k + 1)
+            out[i]["E_a"] = out[i]["E_b"] = -(k + 1.0) * N
+        state["m"] += 1
+        return out
+
+    monkeypatch.setattr(ptsg, "pt_init_batch", init)
+    monkeypatch.setattr(ptsg, "pt_step", lambda ctx, n_hb, n_or: None)
+    monkeypatch.setattr(ptsg, "pt_swap", swap)
+    monkeypatch.setattr(ptsg, "pt_measure", measure)
+    monkeypatch.setattr(ptsg, "pt_get_perms", lambda ctx: list(state["perm"]))
+    monkeypatch.setattr(ptsg, "pt_free", lambda ctx: None)
+    run = fss.simulate(L, S, temps, R, steps, every, 5, "bimodal", 1.0, chiral=True, log=lambda msg: None)
+    n = steps // every
+    assert run["bins"][0] == (n // 2, n) and run["counts"][0] == n // 2
+    last = range(n // 2, n)
+    for s in range(S):
+        for k in range(T):
+            want = np.mean([q_of(s, k, m) ** 2 for m in last])
+            assert run["means"]["q2"][0][s][k] == pytest.approx(want, rel=1e-12)
+            assert run["means"]["qk2"][0][s][k] == pytest.approx(0.04, rel=1e-12)
+            assert run["means"]["cg2"][0][s][k] == pytest.approx((0.05 * (k + 1)) ** 2, rel=1e-12)
+            assert run["means"]["e"][0][s][k] == pytest.approx(-(k + 1.0), rel=1e-12)
+    # a fresh random permutation at every swap: the slots are uncorrelated in time
+    assert len(run["tau_walk"]) == S
+    assert all(0.3 < t / every < 0.8 for t in run["tau_walk"]), run["tau_walk"]
