@@ -226,7 +226,9 @@ def report(runs, temps, couplings, D):
     return result
 
 
-def main(argv=None):
+def make_parser():
+    """The command line; its defaults are the paper's D = 1 protocol at L = 8
+    and 16 (Table I), on one 28-temperature grid for both sizes."""
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--L", type=int, nargs="+", default=[8, 16])
     ap.add_argument("--samples", type=int, default=256)
@@ -242,7 +244,11 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write per-sample bin means (npz)")
     ap.add_argument("--combine", nargs="+", default=None, help="analyse saved batches together (no GPU)")
-    args = ap.parse_args(argv)
+    return ap
+
+
+def main(argv=None):
+    args = make_parser().parse_args(argv)
     if args.combine:
         runs = load_runs(args.combine)
         result = report(runs, runs[0]["temps"], args.couplings, args.D)

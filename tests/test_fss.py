@@ -194,3 +194,32 @@ def test_simulate_host_logic_with_a_scripted_library(monkeypatch):
     # a fresh random permutation at every swap: the slots are uncorrelated in time
     assert len(run["tau_walk"]) == S
     assert all(0.3 < t / every < 0.8 for t in run["tau_walk"]), run["tau_walk"]
+
+
+def _table1():
+    import csv
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_run_parameters.csv")
+    with open(path) as fh:
+        rows = [r for r in csv.DictReader(line for line in fh if not line.startswith("#"))]
+    return {(float(r["D"]), int(r["L"])): r for r in rows}
+
+
+def test_cli_defaults_follow_table_1():
+    """The driver's defaults are the paper's D = 1 protocol at L = 8 and 16
+    (Table I): T in [0.877, 1.28], 20480 and 40960 MCS, two replicas, and the
+    28 temperatures Table I gives for L = 16 (Table I gives 10 at L = 8; the
+    driver puts both sizes on the larger grid, since the crossing fits compare
+    the two sizes at the same temperatures)."""
+    t1 = _table1()
+    args = fss.make_parser().parse_args([])
+    assert args.L == [8, 16] and args.replicas == 2 and args.D == 1.0 and args.couplings == "bimodal"
+    for L, steps in zip(args.L, args.steps):
+        row = t1[(1.0, L)]
+        assert steps == int(row["n_mcs_min"])
+        assert args.temps[0] == float(row["T_min"]) and args.temps[1] == float(row["T_max"])
+    assert args.temps[2] == int(t1[(1.0, 16)]["n_temps"])
+    # the D = 0.5 runs of the same sizes use Table I's grid and lengths through the options
+    row8, row16 = t1[(0.5, 8)], t1[(0.5, 16)]
+    assert (row8["T_min"], row8["T_max"]) == (row16["T_min"], row16["T_max"]) == ("0.588", "0.8")
+    assert (int(row8["n_mcs_min"]), int(row16["n_mcs_min"])) == (20480, 40960)
