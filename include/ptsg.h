@@ -163,7 +163,9 @@ enum {
      * x = 8b .. 8b+7 in class (b + y + z) mod 2; a sweep updates every
      * class-0 row, then every class-1 row, each row in increasing x with
      * each spin seeing those updated before it.  Heat-bath sweeps stay
-     * checkerboard.  Needs L a multiple of 8 and <= 128 and runs on the
+     * checkerboard.  Needs L = 8 or a multiple of 16 (an odd number of rows
+     * along x above one would put the first and last row of an x line, which
+     * touch across the boundary, in one class), L <= 128, and runs on the
      * chain-lane mapping (excludes PT_F_SITE_LANES, PT_F_RESIDENT,
      * PT_F_PLAIN). */
     PT_F_ROW_OR = 128u

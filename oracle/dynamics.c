@@ -99,14 +99,21 @@ void or_half_sweep(int L, const double *M, double *s, int colour, int kind,
 /* Row-ordered overrelaxation sweep (the alternative deterministic order of
  * Sec. III and appendix A.3: rows of 8 spins along x, updated one after the
  * other inside a row, rows that share no bond updated together).  Reading
- * taken: row (b, y, z) holds x = 8b .. 8b+7; its class is (b + y + z) mod 2;
- * two rows of one class share no bond (neighbouring rows differ by one in
- * exactly one of b, y, z), so the class-0 rows, then the class-1 rows, in
- * any order.  Inside a row the sites go in increasing x, each seeing the
- * spins already updated before it.  L must be a multiple of 8. */
-void or_row_sweep(int L, const double *M, double *s)
+ * taken: row (b, y, z) holds x = 8b .. 8b+7; its class is (b + y + z) mod 2.
+ * Two rows of one class share no bond when the number of rows along x,
+ * B = L/8, is even (rows that touch differ by one in exactly one of b, y, z;
+ * b = 0 and b = B-1 touch across the periodic boundary and then differ in
+ * parity) or B = 1 (a row is a whole x line, its own neighbour along x).
+ * For odd B >= 3 the rows b = 0 and b = B-1 of one (y, z) share a bond and
+ * fall in the same class, so the class order would not be defined by the
+ * classes alone: such L are refused (return -1).  The class-0 rows, then the
+ * class-1 rows, in any order; inside a row the sites go in increasing x,
+ * each seeing the spins already updated before it.  L must be a multiple
+ * of 8. */
+int or_row_sweep(int L, const double *M, double *s)
 {
     const int B = L / 8;
+    if (L % 8 != 0 || (B > 1 && B % 2 != 0)) return -1;
     for (int cls = 0; cls < 2; ++cls)
         for (int z = 0; z < L; ++z)
             for (int y = 0; y < L; ++y)
@@ -119,6 +126,7 @@ void or_row_sweep(int L, const double *M, double *s)
                         or_overrelax_spin(h, s + 3 * i);
                     }
                 }
+    return 0;
 }
 
 /* Hot start: z = 1 - 2 u1 is uniform on [-1, 1] and the azimuth uniform,

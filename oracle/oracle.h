@@ -62,12 +62,14 @@ double or_u52(uint32_t w0, uint32_t w1); /* (((w0>>6)<<26 | (w1>>6)) + 0.5) * 2^
 /* Fourth counter word for (tag, temperature slot, replica). */
 uint32_t or_ctr3(uint32_t tag, uint32_t tslot, uint32_t rep);
 
+/* Row-ordered overrelaxation sweep: rows of 8 along x in two classes
+ * ((x/8 + y + z) mod 2), sequential in x inside a row.  L must be 8 or a
+ * multiple of 16 (returns -1 otherwise, leaving s unchanged). */
+int or_row_sweep(int L, const double *M, double *s);
+
 /* One checkerboard half-sweep of colour c over one chain.
  * kind 0 = overrelaxation, 1 = heat-bath at inverse temperature beta; the
  * heat-bath draws use counter (i, hb_sweep, sample, ctr3(HB, tslot, rep)). */
-/* Row-ordered overrelaxation sweep: rows of 8 along x in two classes
- * ((x/8 + y + z) mod 2), sequential in x inside a row (L % 8 == 0). */
-void or_row_sweep(int L, const double *M, double *s);
 void or_half_sweep(int L, const double *M, double *s, int colour, int kind,
                    double beta, uint64_t seed, uint32_t hb_sweep,
                    uint32_t sample, uint32_t tslot, uint32_t rep);

@@ -44,6 +44,7 @@ def lib():
         L.or_init_spins.argtypes = [C.c_int, _dp, C.c_uint64, C.c_uint32, C.c_uint32,
                                     C.c_uint32]
         L.or_row_sweep.argtypes = [C.c_int, _dp, _dp]
+        L.or_row_sweep.restype = C.c_int
         L.or_pt_pass.argtypes = [C.c_int, _dp, _dp, _i32p, C.c_uint64, C.c_uint32,
                                  C.c_uint32, C.c_uint32]
         L.or_pt_pass.restype = C.c_int
@@ -151,10 +152,13 @@ def pt_pass(beta, E, perm, seed, pass_index, sample, rep):
 
 
 def row_sweep(L, M, s):
-    """Row-ordered overrelaxation sweep, in place (s: float64 [N][3])."""
-    assert L % 8 == 0 and s.dtype == np.float64 and s.flags.c_contiguous
+    """Row-ordered overrelaxation sweep, in place (s: float64 [N][3]).
+    L must be 8 or a multiple of 16 (ValueError otherwise: for an odd number
+    of 8-site rows along x above one, two rows of one class touch)."""
+    assert s.dtype == np.float64 and s.flags.c_contiguous
     M = _f64(M)
-    lib().or_row_sweep(L, _d(M), _d(s))
+    if lib().or_row_sweep(L, _d(M), _d(s)) != 0:
+        raise ValueError(f"row order needs L = 8 or a multiple of 16, got L = {L}")
 
 
 def overlaps(L, sa, sb):

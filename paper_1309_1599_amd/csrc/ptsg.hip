@@ -213,8 +213,11 @@ std::string validate(const pt_batch_desc *d)
             if (k > 0 && !(t > d->temps[s][k - 1]))
                 return "sample " + std::to_string(s) + ": temperatures must be strictly ascending";
         }
-        if ((d->flags & PT_F_ROW_OR) && (L % 8 != 0 || L > 128))
-            return "sample " + std::to_string(s) + ": PT_F_ROW_OR needs L a multiple of 8 and <= 128";
+        // Rows of 8 along x fall in classes (x/8 + y + z) mod 2; with an odd
+        // number of rows along x above one, the first and last row of an x
+        // line touch across the boundary in the same class.
+        if ((d->flags & PT_F_ROW_OR) && ((L != 8 && L % 16 != 0) || L > 128))
+            return "sample " + std::to_string(s) + ": PT_F_ROW_OR needs L = 8 or a multiple of 16, and L <= 128";
         if ((d->flags & PT_F_BIMODAL) && bimodal_D(L, d->couplings[s]) == 0.0f)
             return "sample " + std::to_string(s) +
                    ": PT_F_BIMODAL needs every bond to be J*1 + D_sym with J = +-1 and D_ab = +-D, D > 0";

@@ -4,7 +4,9 @@
 // rows of 8 spins along x, updated one after the other inside a row, and
 // rows that share no bond updated together.  Row (b, y, z) holds
 // x = 8b .. 8b+7 and belongs to class (b + y + z) mod 2; neighbouring rows
-// differ by one in exactly one of b, y, z, so a class is a set of
+// differ by one in exactly one of b, y, z (b = 0 and b = L/8 - 1 touch
+// across the periodic boundary, and differ in parity because the host
+// accepts only L = 8 or L a multiple of 16), so a class is a set of
 // independent rows and a sweep is class 0, then class 1.
 //
 // One wave = one row for 64 chains of a sample (lane = chain, as in the

@@ -166,7 +166,8 @@ def test_row_order_flag_validation(lib):
     ok = ptsg.pt_workspace_size([16], [np.zeros((3, 16 ** 3, 3, 3), np.float32)], temps, 2,
                                 flags=ptsg.PT_F_ROW_OR)
     assert ok > 0
-    for L, flags in ((12, ptsg.PT_F_ROW_OR), (16, ptsg.PT_F_ROW_OR | ptsg.PT_F_SITE_LANES),
+    for L, flags in ((12, ptsg.PT_F_ROW_OR), (24, ptsg.PT_F_ROW_OR), (40, ptsg.PT_F_ROW_OR),
+                     (16, ptsg.PT_F_ROW_OR | ptsg.PT_F_SITE_LANES),
                      (16, ptsg.PT_F_ROW_OR | ptsg.PT_F_PLAIN)):
         cpl = [np.zeros((3, L ** 3, 3, 3), np.float32)]
         assert ptsg.pt_workspace_size([L], cpl, temps, 2, flags=flags) == 0

@@ -4,8 +4,8 @@ states the GPU saw (each spin depends on the FP32 spins updated before it
 in its row, so rounding is carried along the row; the per-update replay
 holds each FP32 update to the single-update bound, and the whole sweep is
 also compared with a looser bound) for L = 8 (where a
-row is a whole x line and wraps onto itself; L = 16, an even number of
-x-blocks; L = 24, an odd number), energies of the resulting states, energy
+row is a whole x line and wraps onto itself), L = 16 and 32 (two and four
+rows along x; an odd number above one is refused), energies of the resulting states, energy
 conservation over many sweeps, a captured step replayed against the eager
 one, and the flag's validation."""
 import numpy as np
@@ -51,7 +51,7 @@ def _replay_each_update(L, M, s0, gpu):
     return ref, hmag
 
 
-@pytest.mark.parametrize("L", [8, 16, 24])
+@pytest.mark.parametrize("L", [8, 16, 32])
 def test_row_sweep_matches_oracle(L):
     T, R, seed = 3, 2, 700 + L
     temps = inputs.geometric_temps(0.6, 1.6, T)
@@ -104,7 +104,7 @@ def test_row_order_conserves_energy_and_differs_from_checkerboard():
 
 
 def test_row_order_graph_replays_match_eager():
-    L, T, R, seed = 24, 3, 2, 780
+    L, T, R, seed = 32, 3, 2, 780
     temps = [inputs.geometric_temps(0.7, 1.5, T)]
     cpl = [inputs.gaussian_couplings(L, seed)]
     eager = ptsg.pt_init_batch([L], cpl, temps, R, seed, flags=ptsg.PT_F_ROW_OR)

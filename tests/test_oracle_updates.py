@@ -211,6 +211,52 @@ def test_schwinger_dyson_lattice_equilibrium(orc):
     assert abs(vals.mean()) < 4 * err, (vals.mean(), err)
 
 
+# ---- hot start (Sec. II.A: the runs start from random unit vectors)
+
+def _hot_start_sample():
+    """Spins of four chains (different sample, slot and replica) at L = 32:
+    131072 unit vectors."""
+    L = 32
+    keys = [(0, 0, 0), (0, 5, 0), (0, 0, 1), (7, 0, 0)]  # each differs from the first in one key
+    return np.concatenate([O.init_spins(L, 130915, s, j, r) for s, j, r in keys]), L, keys
+
+
+def test_hot_start_is_uniform_on_the_sphere():
+    """Uniform on the sphere means (Archimedes) every Cartesian component is
+    uniform on [-1, 1], the azimuth about any axis is uniform on [0, 2 pi),
+    <s_a s_b> = delta_ab / 3, and |s| = 1.  Each is tested on 131072 spins:
+    KS tests of the three components and of the azimuths about z and about
+    x, the second-moment tensor within 5 standard errors (the variance of
+    s_a^2 is 4/45 and of s_a s_b 1/15 for the uniform law)."""
+    s, _, _ = _hot_start_sample()
+    n = len(s)
+    assert np.abs(np.linalg.norm(s, axis=1) - 1.0).max() < 1e-14
+    for a in range(3):
+        assert stats.kstest(s[:, a], stats.uniform(-1.0, 2.0).cdf).pvalue > 1e-4, a
+    phi_z = np.mod(np.arctan2(s[:, 1], s[:, 0]), 2 * np.pi)
+    phi_x = np.mod(np.arctan2(s[:, 2], s[:, 1]), 2 * np.pi)
+    for phi in (phi_z, phi_x):
+        assert stats.kstest(phi, stats.uniform(0.0, 2 * np.pi).cdf).pvalue > 1e-4
+    Q = s.T @ s / n
+    for a in range(3):
+        assert abs(Q[a, a] - 1.0 / 3.0) < 5 * np.sqrt(4.0 / 45.0 / n), Q
+        for b in range(a + 1, 3):
+            assert abs(Q[a, b]) < 5 * np.sqrt(1.0 / 15.0 / n), Q
+
+
+def test_hot_start_streams_are_distinct_and_reproducible():
+    """Each (sample, slot, replica) has its own stream: the four chains are
+    uncorrelated (the mean of s.s' over sites has standard error
+    1/sqrt(3 N)), and a repeated call gives the same spins bit for bit."""
+    s, L, keys = _hot_start_sample()
+    N = L ** 3
+    chains = s.reshape(len(keys), N, 3)
+    for p in range(len(keys)):
+        for q in range(p + 1, len(keys)):
+            assert abs((chains[p] * chains[q]).sum(axis=1).mean()) < 5 / np.sqrt(3 * N), (p, q)
+    np.testing.assert_array_equal(chains[1], O.init_spins(L, 130915, *keys[1]))
+
+
 # ---- row-ordered overrelaxation (the paper's alternative deterministic order)
 
 def _row_sweep_by_hand(L, M, s):
@@ -243,22 +289,45 @@ def test_row_sweep_is_the_stated_order():
     assert np.abs(a - c).max() > 1e-3
 
 
-def test_row_sweep_rows_of_a_class_commute():
-    """Rows of one class share no bond: updating them in reverse order gives
-    the same spins (bit for bit), while reversing x inside a row does not."""
-    L = 16
-    M = inputs.gaussian_couplings(L, 42).astype(np.float64)
-    s0 = O.init_spins(L, 42, 0, 0, 0)
-    a = s0.copy()
-    O.row_sweep(L, M, a)
-    b = s0.copy()
+def _row_sweep_reversed(L, M, s):
+    """The row sweep with the rows of each class visited in reverse order."""
     for cls in (0, 1):
         rows = [(b_, y, z) for z in range(L) for y in range(L) for b_ in range(L // 8) if (b_ + y + z) % 2 == cls]
         for b_, y, z in reversed(rows):
             for x in range(8 * b_, 8 * b_ + 8):
                 i = x + L * (y + L * z)
-                b[i] = O.overrelax_spin(O.local_field(L, M, b, i), b[i])
+                s[i] = O.overrelax_spin(O.local_field(L, M, s, i), s[i])
+
+
+@pytest.mark.parametrize("L", [16, 32])
+def test_row_sweep_rows_of_a_class_commute(L):
+    """Rows of one class share no bond (L/8 even): updating them in reverse
+    order gives the same spins, bit for bit."""
+    M = inputs.gaussian_couplings(L, 42).astype(np.float64)
+    s0 = O.init_spins(L, 42, 0, 0, 0)
+    a = s0.copy()
+    O.row_sweep(L, M, a)
+    b = s0.copy()
+    _row_sweep_reversed(L, M, b)
     np.testing.assert_array_equal(a, b)
+
+
+def test_row_classes_touch_for_an_odd_row_count():
+    """L = 24: three rows along x, so rows b = 0 and b = 2 of one (y, z) are
+    x-neighbours across the periodic boundary and share a class.  Visiting a
+    class in reverse order then changes the result (the two orders differ
+    by much more than rounding), so the classes do not define the sweep and
+    the oracle refuses such L."""
+    L = 24
+    M = inputs.gaussian_couplings(L, 44).astype(np.float64)
+    s0 = O.init_spins(L, 44, 0, 0, 0)
+    a = s0.copy()
+    _row_sweep_by_hand(L, M, a)
+    b = s0.copy()
+    _row_sweep_reversed(L, M, b)
+    assert np.abs(a - b).max() > 1e-3
+    with pytest.raises(ValueError):
+        O.row_sweep(L, M, s0.copy())
 
 
 def test_row_sweep_conserves_energy():
