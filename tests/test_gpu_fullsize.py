@@ -1,6 +1,14 @@
-"""Parity at the benchmark's full size and launch configuration (L = 64,
-8 samples x 32 temperatures x 4 replicas), on sampled outputs the oracle
-computes one by one.
+"""Parity at the presets' full sizes and in the launch configuration the
+library picks for them, on sampled outputs the oracle computes one by one:
+
+- L64x8: L = 64, 8 samples x 32 temperatures x 4 replicas (chain lanes);
+- L32x64: L = 32, 64 samples x 24 temperatures x 4 replicas (site lanes,
+  96 chains per workgroup: the software-pipelined chain loop at its full
+  length);
+- mixedL: L in {8, 12, 16, 24, 32, 48}, 16 samples each (resident lattices
+  up to L = 16, site lanes with 6 and 28 chains per workgroup at L = 24 and
+  32, chain lanes at L = 48), with the automatic mappings and with the
+  autotuner's.
 
 Within a half-sweep every site of the active colour is updated from its
 neighbours of the other colour only, so a site's new value is a function of
@@ -8,8 +16,9 @@ neighbours of the other colour only, so a site's new value is a function of
 sites the neighbours are the pre-sweep state; for colour-1 sites they are
 the post-sweep colour-0 values.  The oracle recomputes sampled sites from
 exactly those inputs, which checks the kernel without any trajectory
-divergence.  Energies, the tempering pass and measurement records are
-checked on whole chains.
+divergence.  The sampled chains include the first and last chain of a
+workgroup and both sides of a workgroup boundary.  Energies, the tempering
+pass and measurement records are checked on whole chains.
 """
 import numpy as np
 import pytest
@@ -20,39 +29,71 @@ from paper_1309_1599_amd import inputs, ptsg
 
 pytestmark = pytest.mark.gpu
 
-PRESET = "L64x8"
-CHAINS = [(0, 0, 0), (3, 2, 17), (7, 3, 31)]  # (sample, replica, slot)
 N_SITES = 1500
 
 
-@pytest.fixture(scope="module")
-def big():
+def _chains_of(name, Ls, temps, R):
+    """Sampled (sample, replica, slot) triples.  Before the first swap chain
+    (r, j) sits at slot j, so local chain index r*T + k names the workgroup
+    position."""
+    if name == "L64x8":
+        return [(0, 0, 0), (3, 2, 17), (7, 3, 31)]
+    if name == "L32x64":
+        # 96 chains per workgroup: first, second, middle and last chain
+        return [(0, 0, 0), (0, 0, 1), (31, 2, 0), (63, 3, 23)]
+    out = []
+    for L in sorted(set(Ls)):
+        s0 = Ls.index(L)
+        T = len(temps[s0])
+        last = len(Ls) - 1 - Ls[::-1].index(L)
+        # local chains 5/6 and 27/28 straddle the 6- and 28-chain workgroups
+        # of L = 24 and 32; the last chain of the last sample of every class
+        for j in (5, 6, 27, 28):
+            if j < R * T and (L in (24, 32)):
+                out.append((s0, j // T, j % T))
+        out.append((last, R - 1, T - 1))
+        out.append((s0, 0, 0))
+    return out
+
+
+PRESETS = [("L64x8", 0), ("L32x64", 0), ("mixedL", 0), ("mixedL", ptsg.PT_F_AUTOTUNE)]
+
+
+@pytest.fixture(scope="module", params=PRESETS, ids=["L64x8", "L32x64", "mixedL", "mixedL-autotune"])
+def big(request):
     import torch
     assert torch.cuda.is_available()
-    Ls, cpl, temps, R, seed = inputs.preset_inputs(PRESET)
-    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed)
-    yield dict(ctx=ctx, L=Ls[0], cpl=cpl, temps=temps, R=R, seed=seed)
+    name, flags = request.param
+    Ls, cpl, temps, R, seed = inputs.preset_inputs(name)
+    print(f"[fullsize] preset {name} flags {flags}", flush=True)
+    ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
+    maps = {L: ptsg.pt_get_mapping(ctx, Ls.index(L)) for L in sorted(set(Ls))}
+    print(f"[fullsize] mappings by L: {maps}", flush=True)
+    yield dict(ctx=ctx, Ls=Ls, cpl=cpl, temps=temps, R=R, seed=seed, name=name,
+               chains=_chains_of(name, Ls, temps, R))
     ptsg.pt_free(ctx)
 
 
 def _check_sweep(b, kind):
-    ctx, L = b["ctx"], b["L"]
-    N = L ** 3
-    col = colours(L)
+    ctx = b["ctx"]
     rng = np.random.default_rng(5 + kind)
     hb = ptsg.pt_get_counters(ctx)[0]
-    before = {c: ptsg.pt_get_spins(ctx, *c) for c in CHAINS}
+    before = {c: ptsg.pt_get_spins(ctx, *c) for c in b["chains"]}
     ptsg.pt_step(ctx, 1 if kind == 1 else 0, 0 if kind == 1 else 1)
     E = ptsg.pt_get_energy(ctx)
     key = [b["seed"] & 0xFFFFFFFF, b["seed"] >> 32]
     worst = 0.0
-    for (s, r, k) in CHAINS:
+    for (s, r, k) in b["chains"]:
+        L = b["Ls"][s]
+        N = L ** 3
+        col = colours(L)
         M = b["cpl"][s].astype(np.float64)
         after = ptsg.pt_get_spins(ctx, s, r, k)
         mixed = np.where(col[:, None] == 0, after, before[(s, r, k)]).astype(np.float64)
         pre0 = before[(s, r, k)].astype(np.float64)
         beta = 1.0 / b["temps"][s][k]
-        for i in rng.choice(N, N_SITES, replace=False):
+        sites = list(rng.choice(N, min(N, N_SITES), replace=False)) + [0, N - 1]
+        for i in sites:
             state = pre0 if col[i] == 0 else mixed
             h = O.local_field(L, M, state, int(i))
             if kind == 0:
@@ -94,12 +135,13 @@ def test_fullsize_tempering(big):
 
 
 def test_fullsize_measure_sampled_records(big):
-    ctx, L = big["ctx"], big["L"]
+    ctx = big["ctx"]
     recs = ptsg.pt_measure(ctx, ptsg.PT_M_ALL)
-    assert len(recs) == ctx.n_records == 8 * 32 * 6
-    for n in (0, 777, len(recs) - 1):
+    assert len(recs) == ctx.n_records
+    for n in sorted({0, len(recs) // 3, len(recs) // 2 + 5, len(recs) - 1}):
         g = recs[n]
         s, k, a, bb = int(g["sample"]), int(g["tslot"]), int(g["rep_a"]), int(g["rep_b"])
+        L = big["Ls"][s]
         sa = ptsg.pt_get_spins(ctx, s, a, k).astype(np.float64)
         sb = ptsg.pt_get_spins(ctx, s, bb, k).astype(np.float64)
         ref = O.overlaps(L, sa, sb)
