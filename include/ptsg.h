@@ -210,6 +210,19 @@ pt_status pt_swap(pt_ctx *ctx);
  * PT_M_CHIRAL need n_replicas >= 2 (PT_ESTATE).  Synchronous. */
 pt_status pt_measure(pt_ctx *ctx, unsigned what, pt_meas *out, size_t cap, size_t *n_out);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the records of
+ * pt_measure, written to d_out, a DEVICE array of cap pt_meas the caller
+ * owns, asynchronously on the context's stream.  No allocation, no host copy,
+ * no synchronisation.  The plane partials go to a fixed 8 MB device array of
+ * the library (one per device, held until the process ends; records are
+ * processed in chunks that fit it, so any batch pt_init_batch accepts fits),
+ * and chain-lane samples are read in place.  Every call on one device shares
+ * that array: calls that overlap on one device (different streams, threads
+ * or contexts) race.  PT_ENOMEM if cap is below the record count; the other
+ * errors as pt_measure's.  The records equal pt_measure's. */
+pt_status pt_measure_noalloc(pt_ctx *ctx, unsigned what, pt_meas *d_out, size_t cap);
+
 /* Spins of the chain at (sample, replica, slot), host [N][3] FP32.
  * pt_set_spins copies them in (no normalisation) and refreshes that
  * sample's energies.  Synchronous. */

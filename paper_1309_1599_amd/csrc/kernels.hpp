@@ -141,8 +141,9 @@ struct MeasParams {
     const double *twid;          // per lattice: cos(2 pi n/L), then sin, n < L
     const double *E, *betas;
     const int *beta_base;
-    double *part;                // [n_records][Lmax][kPlaneQ]
-    int Lmax, n_records;
+    double *part;                // [record - part_rec0][Lmax][kPlaneQ]
+    int Lmax, n_records;         // finalisation covers records [rec0, n_records)
+    int part_rec0;               // record whose partials sit at the start of `part`
     unsigned what;
     void *out;                   // device pt_meas[n_records]
     // Sample `stage_sample` (-1: none) is read from `stage`, a site-lane
@@ -191,7 +192,8 @@ int cl_blocks(int L, int split);
 hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, float *canon,
                            bool to_canon, hipStream_t st);
 // Plane kernels for records [rec0, rec0 + n) (lattices up to L), then, once
-// all records are done, the per-record finalisation.
+// all records are done, the per-record finalisation of records
+// [rec0, n_records).
 hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st);
 hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st);
 // Copy the chains of a chain-lane sample into the site-lane layout (the

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kMeasBlock) void overlap_plane_kernel(MeasParams P)
             }
         }
     }
-    block_store<45>(acc, P.part + (static_cast<int64_t>(rec) * P.Lmax + z) * kPlaneQ);
+    block_store<45>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ);
 }
 
 __device__ __forceinline__ double chirality(const Chain &c, int x, int y, int z, int mu)
@@ -208,19 +208,19 @@ __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
             acc[18] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
         }
     }
-    block_store<19>(acc, P.part + (static_cast<int64_t>(rec) * P.Lmax + z) * kPlaneQ + kOverlapQ);
+    block_store<19>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kOverlapQ);
 }
 
 __global__ void finalize_kernel(MeasParams P)
 {
-    const int rec = blockIdx.x * blockDim.x + threadIdx.x;
+    const int rec = P.rec0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
     if (rec >= P.n_records) return;
     const int *rd = P.rec + 4 * rec;
     const int s = rd[0], k = rd[1], ra = rd[2], rb = rd[3];
     const int L = P.L[s], T = P.n_temps[s];
     const double invN = 1.0 / (static_cast<double>(L) * L * L);
     const double *cw = P.twid + P.twid_base[s], *sw = cw + L;
-    const double *part = P.part + static_cast<int64_t>(rec) * P.Lmax * kPlaneQ;
+    const double *part = P.part + static_cast<int64_t>(rec - P.part_rec0) * P.Lmax * kPlaneQ;
     pt_meas &m = static_cast<pt_meas *>(P.out)[rec];
     m.sample = s;
     m.tslot = k;
@@ -313,8 +313,9 @@ hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t
 
 hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st)
 {
-    if (p.n_records == 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3((p.n_records + 63) / 64), dim3(64), 0, st, p);
+    const int n = p.n_records - p.rec0;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3((n + 63) / 64), dim3(64), 0, st, p);
     return hipGetLastError();
 }
 

@@ -318,6 +318,33 @@ struct Event {
     hipEvent_t a = nullptr, b = nullptr;
 };
 
+// Measurement partials of pt_measure_noalloc: a fixed device array instead
+// of the context's workspace (8 MB, every device the library runs on holds
+// one until the process ends).  Host code never passes `scratch` itself to a
+// kernel: its device address, per device, comes from hipGetSymbolAddress.
+constexpr size_t kScratchDoubles = size_t(1) << 20;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;   // device -> address of its `scratch`
+
+// Address of `scratch` on `device` (which must be current); looked up once
+// per device.
+pt_status scratch_on(int device, double **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PT_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(device, static_cast<double *>(p)).first;
+    }
+    *out = it->second;
+    return PT_OK;
+}
+
 }  // namespace
 
 struct pt_ctx {
@@ -798,6 +825,11 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     } guard{c};
 
     if (hipGetDevice(&c->device) != hipSuccess) return fail(PT_EDEVICE, "no HIP device");
+    {
+        double *unused = nullptr;
+        pt_status st_scratch = scratch_on(c->device, &unused);
+        if (st_scratch != PT_OK) return st_scratch;
+    }
     c->stream = static_cast<hipStream_t>(d->stream);
     c->seed = d->seed;
     c->plan = make_plan(d, forced);
@@ -1276,6 +1308,65 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
     PT_HIP(hipMemcpyAsync(out, c->meas, sizeof(pt_meas) * P.n_records, hipMemcpyDeviceToHost,
                           c->stream));
     PT_HIP(hipStreamSynchronize(c->stream));
+    return PT_OK;
+}
+
+// pt_measure's records written to a device buffer, with the plane partials
+// in the fixed `scratch` array (records in chunks that fit it) and
+// chain-lane samples read in place (no staging copy): nothing is allocated,
+// nothing is copied to the host, nothing waits.
+pt_status pt_measure_noalloc(pt_ctx *c, unsigned what, pt_meas *d_out, size_t cap)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (what & ~static_cast<unsigned>(PT_M_ALL)) return fail(PT_EINVAL, "unknown measurement bits");
+    const Plan &P = c->plan;
+    if ((what & (PT_M_OVERLAP | PT_M_CHIRAL)) && P.R < 2)
+        return fail(PT_ESTATE, "overlap and chirality need n_replicas >= 2");
+    if (P.n_records == 0) return PT_OK;
+    if (!d_out) return fail(PT_EINVAL, "output buffer is NULL");
+    if (cap < static_cast<size_t>(P.n_records))
+        return fail(PT_ENOMEM, "output holds " + std::to_string(cap) + " records, " +
+                                   std::to_string(P.n_records) + " needed");
+    const size_t per_record = static_cast<size_t>(P.Lmax) * kPlaneQ;
+    if (per_record > kScratchDoubles)
+        return fail(PT_EUNSUPPORTED, "one record's partials (" + std::to_string(per_record * 8) +
+                                         " bytes) exceed the fixed scratch of " +
+                                         std::to_string(kScratchDoubles * 8) + " bytes");
+    double *part = nullptr;
+    if ((st = scratch_on(c->device, &part)) != PT_OK) return st;
+    const int chunk = static_cast<int>(std::min<size_t>(kScratchDoubles / per_record, P.n_records));
+    MeasParams m{};
+    m.spins = c->spins;
+    m.cpls = c->cpls;
+    m.rec = c->rec;
+    m.perm = c->perm;
+    m.perm_base = c->d_perm_base;
+    m.n_temps = c->d_T;
+    m.L = c->d_L;
+    m.chain_base = c->d_chain_base;
+    m.twid_base = c->d_twid_base;
+    m.spin_base = c->d_spin_base;
+    m.cpls_base = c->d_cpls_base;
+    m.lanes = c->d_lanes;
+    m.twid = c->twid;
+    m.E = c->E;
+    m.betas = c->betas;
+    m.beta_base = c->d_beta_base;
+    m.part = part;
+    m.Lmax = P.Lmax;
+    m.what = what;
+    m.out = d_out;
+    m.stage = nullptr;
+    m.stage_sample = -1;
+    for (int r0 = 0; r0 < P.n_records; r0 += chunk) {
+        const int n = std::min(chunk, P.n_records - r0);
+        m.rec0 = r0;
+        m.part_rec0 = r0;
+        m.n_records = r0 + n;
+        PT_HIP(launch_measure_records(m, n, P.Lmax, c->stream));
+        PT_HIP(launch_measure_finalize(m, c->stream));
+    }
     return PT_OK;
 }
 

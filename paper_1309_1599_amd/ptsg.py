@@ -32,6 +32,7 @@ assert MEAS_DTYPE.itemsize == 744
 
 # Every symbol the C ABI exports (include/ptsg.h).
 EXPORTS = ["pt_init", "pt_workspace_size", "pt_init_batch", "pt_step", "pt_swap", "pt_measure",
+           "pt_measure_noalloc",
            "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_perms", "pt_get_energy", "pt_get_counters",
            "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping",
            "pt_save", "pt_load", "pt_free", "pt_last_error"]
@@ -77,6 +78,7 @@ def load_library(path=LIB_PATH):
         "pt_step": (i, [vp, i, i]),
         "pt_swap": (i, [vp]),
         "pt_measure": (i, [vp, C.c_uint, vp, sz, C.POINTER(sz)]),
+        "pt_measure_noalloc": (i, [vp, C.c_uint, vp, sz]),
         "pt_get_spins": (i, [vp, i, i, i, C.POINTER(C.c_float)]),
         "pt_set_spins": (i, [vp, i, i, i, C.POINTER(C.c_float)]),
         "pt_get_perm": (i, [vp, i, i, C.POINTER(C.c_int32)]),
@@ -212,6 +214,12 @@ def pt_measure(ctx, what=PT_M_ALL):
     _check(load_library().pt_measure(ctx.ptr, int(what), out.ctypes.data_as(C.c_void_p),
                                      len(out), C.byref(n)))
     return out[: n.value]
+
+
+def pt_measure_noalloc(ctx, what, d_out, cap):
+    """Records into a device buffer (address d_out, room for cap records),
+    queued on the context's stream; nothing is allocated or copied."""
+    _check(load_library().pt_measure_noalloc(ctx.ptr, int(what), C.c_void_p(int(d_out)), int(cap)))
 
 
 def pt_get_spins(ctx, sample, rep, tslot):
