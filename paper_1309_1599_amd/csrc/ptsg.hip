@@ -43,6 +43,14 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
+// An integer tuning knob from the environment, clamped to [lo, hi].
+int env_int(const char *name, int dflt, int lo, int hi)
+{
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::min(hi, std::max(lo, std::atoi(v)));
+}
+
 // One lattice class: samples sharing L, the number of temperatures and the
 // kernel mapping, swept by the same launches.
 enum Mapping { kSiteLanes = 0, kChainLanes = 1, kResident = 2 };
@@ -53,7 +61,8 @@ struct LatticeClass {
     int split = 1;                   // chain lanes: waves per packed row
     int strip = 0;                   // chain lanes: y-rows per strip of the row order
     int blocks = 0;                  // workgroups per (sample or item) and half-sweep
-    int batch = 1;                   // chain lanes: items per launch (Infinity Cache budget)
+    int batch = 1;                   // chain lanes: items per launch; site lanes: samples per launch
+                                     // (both sized to the Infinity Cache budget)
     std::vector<int> samples;
     int *d_samples = nullptr;
     std::vector<int> items;          // chain lanes: (sample, group) pairs
@@ -89,6 +98,18 @@ int max_split(int L)
     for (int s = 2; s <= 8; s *= 2)
         if (Lh % s == 0 && Lh / s >= 2) best = s;
     return best;
+}
+
+// Samples per site-lane launch within the cache budget (spins of all chains
+// plus the packed couplings, or their byte codes).  Every sweep of a step
+// runs on one batch before the next, so the half-sweeps after the first
+// find the batch in the Infinity Cache instead of HBM.
+int site_batch(int L, int C, bool codes, int n_samples)
+{
+    const int64_t N = static_cast<int64_t>(L) * L * L;
+    const int64_t sample = static_cast<int64_t>(C) * 12 * N + (codes ? 8 : 216) * N;
+    const int64_t budget = env_int("PTSG_SITE_BATCH_MB", 192, 1, 1 << 20) * (1ll << 20);
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_samples, budget / sample)));
 }
 
 // Items (64-chain groups) per chain-lane launch within the cache budget.
@@ -544,19 +565,24 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
                             [&](const LaunchTiming &t) { return launch_resident_step(p, n_chains, c->stream, t); });
     }
     if (k.lanes == 1) {
-        uint32_t hb = 0;
-        for (int n = 0; n < total; ++n) {
-            const int kind = kinds[n];
-            for (int colour = 0; colour < 2; ++colour) {
-                const bool energy = n == total - 1 && colour == 1;
-                const SweepParams p = sweep_params(c, k, colour, hb);
-                const int ns = static_cast<int>(k.samples.size());
-                st = timed_launch(c, kind, [&](const LaunchTiming &t) {
-                    return launch_half_sweep(kind, energy, p, ns, c->stream, t);
-                });
-                if (st != PT_OK) return st;
+        // sample-batch-major: every sweep of one batch of samples before the next
+        const int n_samples = static_cast<int>(k.samples.size());
+        for (int first = 0; first < n_samples; first += k.batch) {
+            const int ns = std::min(k.batch, n_samples - first);
+            uint32_t hb = 0;
+            for (int n = 0; n < total; ++n) {
+                const int kind = kinds[n];
+                for (int colour = 0; colour < 2; ++colour) {
+                    const bool energy = n == total - 1 && colour == 1;
+                    SweepParams p = sweep_params(c, k, colour, hb);
+                    p.samples = k.d_samples + first;
+                    st = timed_launch(c, kind, [&](const LaunchTiming &t) {
+                        return launch_half_sweep(kind, energy, p, ns, c->stream, t);
+                    });
+                    if (st != PT_OK) return st;
+                }
+                if (kind == kHeatbath) ++hb;
             }
-            if (kind == kHeatbath) ++hb;
         }
     } else {
         // chain-group-major: every sweep of one batch of items before the next
@@ -616,9 +642,10 @@ pt_status refresh_energies(pt_ctx *c)
 int choose_group(int H, int C, int n_samples)
 {
     const int blocks = (H + kSweepBlock - 1) / kSweepBlock * n_samples;
+    const int want = env_int("PTSG_SITE_WGS", 2048, 1, 1 << 20);
     int G = std::min(C, kMaxGroup);
-    while (G > 1 && static_cast<int64_t>(blocks) * ((C + G - 1) / G) < 2048) G = (G + 1) / 2;
-    return G;
+    while (G > 1 && static_cast<int64_t>(blocks) * ((C + G - 1) / G) < want) G = (G + 1) / 2;
+    return std::min(G, env_int("PTSG_SITE_GROUP", G, 1, kMaxGroup));
 }
 
 void pack_couplings(int L, const float *M, float *out)
@@ -995,7 +1022,10 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                 k.blocks = 1;
             } else if (k.mapping == kSiteLanes) {
                 k.blocks = (H + kSweepBlock - 1) / kSweepBlock;
-                k.G = (d->flags & PT_F_PLAIN) ? 1 : choose_group(H, k.C, static_cast<int>(g.second.size()));
+                const int ns = static_cast<int>(g.second.size());
+                // the plain single-chain form stays one launch over every sample
+                k.batch = (d->flags & PT_F_PLAIN) ? ns : site_batch(k.L, k.C, P.codes[g.second[0]], ns);
+                k.G = (d->flags & PT_F_PLAIN) ? 1 : choose_group(H, k.C, k.batch);
             } else {
                 for (int s : g.second)
                     for (int grp = 0; grp < (k.C + 63) / 64; ++grp) {
