@@ -59,6 +59,19 @@ def pmc_traffic(preset, mapping, expected_hash):
     return float(b.group(1))
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
     """The FP64 oracle as it stands on a bounded sample of the same workload:
     chains of sample 0, each one heat-bath sweep, n_or overrelaxation sweeps
@@ -103,6 +116,7 @@ def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
         "unit": "ps/SU",
         "cores": workers,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "single_thread_value": round(single * 1e12, 1),
         "sample": f"chains on the couplings of sample 0 at L={L} (its temperatures, replica index "
                   f"running on past the workload's where more chains are needed), each 1 heat-bath + "
@@ -118,7 +132,8 @@ def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, w
     ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
     names = {ptsg.PT_F_SITE_LANES: "site", ptsg.PT_F_CHAIN_LANES: "chain", ptsg.PT_F_RESIDENT: "resident"}
     maps = [names[ptsg.pt_get_mapping(ctx, s)] for s in range(len(Ls))]
-    su_per_step = sum((n_hb + n_or) * R * len(t) * L ** 3 for L, t in zip(Ls, temps))
+    su_per_step = sum((n_hb + (L if n_or == ptsg.PT_OR_L else n_or)) * R * len(t) * L ** 3
+                      for L, t in zip(Ls, temps))
 
     def step(t):
         ptsg.pt_step(ctx, n_hb, n_or)
@@ -192,8 +207,8 @@ def main():
         cpl = [inputs.bimodal_couplings(L, 0.5, seed, s) for s, L in enumerate(Ls)]
     n_hb = p["n_hb"]
     mixed = len(set(Ls)) > 1
-    # a mixed batch shares one step: 1 HB + 16 OR + PT
-    n_or = 16 if p["n_or"] is None and mixed else (Ls[0] if p["n_or"] is None else p["n_or"])
+    # the paper's step: 1 HB + L OR + PT, each sample with its own L
+    n_or = (ptsg.PT_OR_L if mixed else Ls[0]) if p["n_or"] is None else p["n_or"]
     every = p["measure_every"]
     flags = {"auto": 0, "tuned": ptsg.PT_F_AUTOTUNE, "site": ptsg.PT_F_SITE_LANES,
              "chain": ptsg.PT_F_CHAIN_LANES, "resident": ptsg.PT_F_RESIDENT}[args.mapping]
@@ -235,6 +250,8 @@ def main():
                                            else "half_sweep_kernel<overrelax>"),
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": (None if rows or bimodal else pmc_traffic(args.preset, mapping, kernel_hash())),
+                "traffic_counters": "FETCH_SIZE + WRITE_SIZE per launch, calibrated on a plain copy: bytes between "
+                                    "the L2 caches and the fabric, Infinity-Cache hits included (not HBM alone)",
                 "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
                 "bytes_per_su": round(bytes_per_su, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
                 "launches": n_l}
@@ -270,7 +287,8 @@ def main():
         "config": {
             "workload": f"{args.preset}: L={sorted(set(Ls))}, {len(Ls)} samples, {n_chains} chains, "
                         + ("bimodal couplings (D = 0.5, one byte per bond); step" if bimodal
-                           else "Gaussian 3x3 couplings; step") + f" = {n_hb} HB + {n_or} OR sweeps + PT pass"
+                           else "Gaussian 3x3 couplings; step") + f" = {n_hb} HB + "
+                        + ("L" if n_or == ptsg.PT_OR_L else str(n_or)) + " OR sweeps + PT pass"
                         + (f", measurement every {every} steps" if every else ""),
             "L": L if not mixed else sorted(set(Ls)), "samples": len(Ls),
             "temperatures": len(temps[0]) if not mixed else sorted({len(t) for t in temps}),
@@ -323,7 +341,7 @@ def main():
                                         "form": "site lanes, one chain per workgroup (couplings "
                                                 "re-read by every chain), same step"}
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(L, cpl[0], temps[0], seed, n_hb, n_or)
+        result["cpu_baseline"] = cpu_baseline(L, cpl[0], temps[0], seed, n_hb, L if n_or == ptsg.PT_OR_L else n_or)
     print(json.dumps(result), flush=True)
 
 

@@ -140,15 +140,20 @@ enum {
     /* Autotuner: for each distinct (L, n_temps) in the batch, time a step of
      * 1 heat-bath + min(L, 32) overrelaxation sweeps of every applicable
      * mapping on a temporary context (enough of those samples for 4096
-     * chains, at least 4, at most 2 GB of spins) and use the fastest; results are cached
-     * for the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
+     * chains, at least 4, at most 2 GB of spins), then of the fastest
+     * mapping with neighbouring tile shapes (site lanes: half and twice the
+     * chains per workgroup; chain lanes: half and twice the waves per packed
+     * row and the y-strips of the row order half and twice as tall), and use
+     * the fastest plan (pt_get_mapping, pt_get_tile); results are cached for
+     * the process.  Ignored when a mapping flag or PT_F_PLAIN is set.
      * Runs kernels on the current device, so pt_workspace_size needs the
      * device too when this flag is set.  When the environment variable
      * PTSG_PLAN_CACHE names a file, results are also looked up there before
      * timing and appended after it, one text line per (device architecture,
      * CU count, L, n_temps, n_replicas, samples timed, PT_F_GRAPHS,
-     * PT_F_BIMODAL); lines that do not parse or name a mapping the lattice
-     * cannot use are skipped, and an unwritable file is not an error. */
+     * PT_F_BIMODAL) holding the mapping and the tile shape; lines that do not
+     * parse or name a plan the lattice cannot use are skipped, and an
+     * unwritable file is not an error. */
     PT_F_AUTOTUNE = 32u,
     /* The paper's coupling family (Sec. II.A): every bond is
      * M = J*1 + D_sym, J = +-1, the six entries D_ab (a <= b) of the
@@ -175,6 +180,12 @@ enum {
  * PT_F_RESIDENT. */
 pt_status pt_get_mapping(pt_ctx *ctx, int sample, unsigned *flag);
 
+/* The tile shape of a sample's sweeps (App. A.3: how the batch is laid on
+ * the GPU), from the heuristics or the autotuner: chains per workgroup
+ * (site lanes: G, chain lanes: 64, resident: 1); waves per packed row and
+ * y-rows per strip of the row visiting order (chain lanes; 0 otherwise). */
+pt_status pt_get_tile(pt_ctx *ctx, int sample, int *chains_per_group, int *split, int *strip);
+
 /* One sample (the single-lattice form of the API).  Equivalent to
  * pt_init_batch with n_samples = 1, the null stream and library-owned
  * memory.  Spins start hot (uniform on the sphere, Philox tag 2). */
@@ -188,8 +199,13 @@ size_t pt_workspace_size(const pt_batch_desc *desc);
 /* Create a context for a batch of samples (see pt_batch_desc). */
 pt_status pt_init_batch(pt_ctx **ctx, const pt_batch_desc *desc);
 
+/* n_or value for the paper's Monte Carlo step in a batch of several L
+ * (Sec. III): every sample runs L overrelaxation sweeps, L its own linear
+ * size. */
+#define PT_OR_L (-1)
+
 /* n_hb heat-bath sweeps then n_or overrelaxation sweeps of every chain
- * (appendix A.1).  A sweep is the checkerboard half-sweep of colour 0
+ * (appendix A.1); n_or = PT_OR_L gives each sample L of them.  A sweep is the checkerboard half-sweep of colour 0
  * ((x+y+z) even) then of colour 1.  Heat-bath draws s from
  * P(s) ~ exp(s.h / T); overrelaxation maps s -> 2 h (h.s)/h^2 - s; both
  * renormalise the spin.  The local field is

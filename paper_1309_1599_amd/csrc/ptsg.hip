@@ -43,14 +43,6 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
-// An integer tuning knob from the environment, clamped to [lo, hi].
-int env_int(const char *name, int dflt, int lo, int hi)
-{
-    const char *v = std::getenv(name);
-    if (!v || !*v) return dflt;
-    return std::min(hi, std::max(lo, std::atoi(v)));
-}
-
 // One lattice class: samples sharing L, the number of temperatures and the
 // kernel mapping, swept by the same launches.
 enum Mapping { kSiteLanes = 0, kChainLanes = 1, kResident = 2 };
@@ -108,7 +100,7 @@ int site_batch(int L, int C, bool codes, int n_samples)
 {
     const int64_t N = static_cast<int64_t>(L) * L * L;
     const int64_t sample = static_cast<int64_t>(C) * 12 * N + (codes ? 8 : 216) * N;
-    const int64_t budget = env_int("PTSG_SITE_BATCH_MB", 192, 1, 1 << 20) * (1ll << 20);
+    const int64_t budget = kCacheBudget;
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_samples, budget / sample)));
 }
 
@@ -246,8 +238,17 @@ std::string validate(const pt_batch_desc *d)
     return "";
 }
 
-// `forced`, when given, holds one mapping per sample (from the autotuner).
-Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
+// A tuned plan of one lattice class: the mapping and its tile shape (0 or
+// -1: the heuristic's choice).
+struct Tile {
+    int mapping = -1;
+    int G = 0;        // site lanes: chains per workgroup
+    int split = 0;    // chain lanes: waves per packed row
+    int strip = -1;   // chain lanes: y-rows per strip of the row order (0: y-major)
+};
+
+// `forced`, when given, holds one tuned plan per sample (from the autotuner).
+Plan make_plan(const pt_batch_desc *d, const std::vector<Tile> *forced = nullptr)
 {
     Plan p;
     p.S = d->n_samples;
@@ -259,7 +260,7 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<int> *forced = nullptr)
         const int L = d->L[s], T = d->n_temps[s];
         const int64_t N = static_cast<int64_t>(L) * L * L;
         const int C = p.R * T;
-        const int mapping = forced ? (*forced)[s] : choose_mapping(d, s);
+        const int mapping = forced ? (*forced)[s].mapping : choose_mapping(d, s);
         const int lanes = mapping == kChainLanes ? 64 : 1;
         const int C_alloc = (C + lanes - 1) / lanes * lanes;
         p.L.push_back(L);
@@ -642,10 +643,9 @@ pt_status refresh_energies(pt_ctx *c)
 int choose_group(int H, int C, int n_samples)
 {
     const int blocks = (H + kSweepBlock - 1) / kSweepBlock * n_samples;
-    const int want = env_int("PTSG_SITE_WGS", 2048, 1, 1 << 20);
     int G = std::min(C, kMaxGroup);
-    while (G > 1 && static_cast<int64_t>(blocks) * ((C + G - 1) / G) < want) G = (G + 1) / 2;
-    return std::min(G, env_int("PTSG_SITE_GROUP", G, 1, kMaxGroup));
+    while (G > 1 && static_cast<int64_t>(blocks) * ((C + G - 1) / G) < 2048) G = (G + 1) / 2;
+    return G;
 }
 
 void pack_couplings(int L, const float *M, float *out)
@@ -730,13 +730,14 @@ pt_status check_ctx(pt_ctx *c)
 }
 
 // Plan cache on disk.  The file that PTSG_PLAN_CACHE names holds one tuned
-// mapping per line:
+// plan per line:
 //   ptsg-plan <version> <arch> <CUs> <L> <n_temps> <n_replicas> <samples timed>
-//             <graphs 0|1> <bimodal 0|1> <site|chain|resident>
+//             <graphs 0|1> <bimodal 0|1> <site|chain|resident> <G> <split> <strip>
 // Lines that do not parse, carry another version, or name a mapping the
 // lattice cannot use are skipped; the last matching line wins.  The version
-// changes whenever the kernels change enough to move the choice.
-constexpr int kPlanVersion = 1;
+// changes whenever the kernels or the tuned parameters change enough to move
+// the choice.
+constexpr int kPlanVersion = 2;
 
 struct PlanKey {
     std::string arch;
@@ -757,30 +758,39 @@ bool mapping_fits(int m, int L)
     return m == kSiteLanes || (m == kChainLanes && L <= 128) || (m == kResident && L <= kRsMaxL);
 }
 
-int plan_cache_lookup(const PlanKey &k)
+bool plan_cache_lookup(const PlanKey &k, Tile &out)
 {
     const char *path = std::getenv("PTSG_PLAN_CACHE");
-    if (!path || !*path) return -1;
+    if (!path || !*path) return false;
     std::ifstream in(path);
     const std::string want = k.text() + ' ';
     std::string line;
-    int found = -1;
+    bool found = false;
     while (std::getline(in, line)) {
         if (line.compare(0, want.size(), want) != 0) continue;
-        const std::string name = line.substr(want.size());
+        std::istringstream rest(line.substr(want.size()));
+        std::string name, extra;
+        Tile t;
+        if (!(rest >> name >> t.G >> t.split >> t.strip) || (rest >> extra)) continue;
         for (int m = 0; m < 3; ++m)
-            if (name == kMappingName[m] && mapping_fits(m, k.L)) found = m;
+            if (name == kMappingName[m] && mapping_fits(m, k.L) && t.G >= 0 && t.G <= kMaxGroup && t.split >= 0 &&
+                t.split <= 8 && t.strip >= -1 && t.strip <= k.L) {
+                t.mapping = m;
+                out = t;
+                found = true;
+            }
     }
     return found;
 }
 
 // Appends one line; a file that cannot be written leaves the tuning result
 // in the process cache only.
-void plan_cache_store(const PlanKey &k, int m)
+void plan_cache_store(const PlanKey &k, const Tile &t)
 {
     const char *path = std::getenv("PTSG_PLAN_CACHE");
     if (!path || !*path) return;
-    const std::string line = k.text() + ' ' + kMappingName[m] + '\n';
+    const std::string line = k.text() + ' ' + kMappingName[t.mapping] + ' ' + std::to_string(t.G) + ' ' +
+                             std::to_string(t.split) + ' ' + std::to_string(t.strip) + '\n';
     if (FILE *f = std::fopen(path, "a")) {
         std::fwrite(line.data(), 1, line.size(), f);
         std::fclose(f);
@@ -793,8 +803,8 @@ extern "C" {
 
 const char *pt_last_error(void) { return g_err.c_str(); }
 
-static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vector<int> *forced);
-static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &mapping);
+static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vector<Tile> *forced);
+static pt_status autotuned_tiles(const pt_batch_desc *d, std::vector<Tile> &tiles);
 
 // The autotuner runs only when no mapping is forced by a flag.
 static bool wants_autotune(const pt_batch_desc *d)
@@ -811,9 +821,9 @@ size_t pt_workspace_size(const pt_batch_desc *desc)
         return 0;
     }
     if (wants_autotune(desc)) {
-        std::vector<int> mapping;
-        if (autotuned_mappings(desc, mapping) != PT_OK) return 0;
-        return make_plan(desc, &mapping).bytes;
+        std::vector<Tile> tiles;
+        if (autotuned_tiles(desc, tiles) != PT_OK) return 0;
+        return make_plan(desc, &tiles).bytes;
     }
     return make_plan(desc).bytes;
 }
@@ -825,15 +835,15 @@ pt_status pt_init_batch(pt_ctx **out, const pt_batch_desc *d)
     const std::string why = validate(d);
     if (!why.empty()) return fail(PT_EINVAL, why);
     if (wants_autotune(d)) {
-        std::vector<int> mapping;
-        pt_status st = autotuned_mappings(d, mapping);
+        std::vector<Tile> tiles;
+        pt_status st = autotuned_tiles(d, tiles);
         if (st != PT_OK) return st;
-        return init_batch(out, d, &mapping);
+        return init_batch(out, d, &tiles);
     }
     return init_batch(out, d, nullptr);
 }
 
-static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vector<int> *forced)
+static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vector<Tile> *forced)
 {
     *out = nullptr;
     const std::string why = validate(d);
@@ -1026,6 +1036,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                 // the plain single-chain form stays one launch over every sample
                 k.batch = (d->flags & PT_F_PLAIN) ? ns : site_batch(k.L, k.C, P.codes[g.second[0]], ns);
                 k.G = (d->flags & PT_F_PLAIN) ? 1 : choose_group(H, k.C, k.batch);
+                if (forced && (*forced)[g.second[0]].G > 0) k.G = std::min((*forced)[g.second[0]].G, k.C);
             } else {
                 for (int s : g.second)
                     for (int grp = 0; grp < (k.C + 63) / 64; ++grp) {
@@ -1036,6 +1047,11 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                 k.batch = cl_batch(k.L, n_items);
                 k.split = choose_split(k.L, k.batch);
                 k.strip = choose_strip(k.L);
+                if (forced) {
+                    const Tile &t = (*forced)[g.second[0]];
+                    if (t.split > 0 && (k.L / 2) % t.split == 0 && (k.L / 2) / t.split >= 2) k.split = t.split;
+                    if (t.strip == 0 || (t.strip > 0 && k.L % t.strip == 0)) k.strip = t.strip;
+                }
                 k.blocks = cl_blocks(k.L, k.split);
                 k.d_items = ditems + 2 * at_items;
                 PT_HIP(hipMemcpy(k.d_items, k.items.data(), k.items.size() * sizeof(int),
@@ -1060,19 +1076,23 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     return PT_OK;
 }
 
-// Autotuner: for each distinct (L, n_temps) of the batch, time a step of one
-// heat-bath and min(L, 32) overrelaxation sweeps of every applicable mapping
-// on a temporary context holding a representative share of those samples
-// (enough for 4096 chains, at least 4, at most 2 GB of spins; best of two,
-// after a warm-up step), and keep the fastest.  The step is long enough for
-// the chain-lane order to pay for its first, cold pass through the cache.
-// Bimodal samples are timed in their byte coding.  Results are cached per
-// (device, L, n_temps, n_replicas, samples timed, graphs, bimodal) for the
-// process, and in the file PTSG_PLAN_CACHE names when it is set.
-static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &mapping)
+// Autotuner: for each distinct (L, n_temps) of the batch, on a temporary
+// context holding a representative share of those samples (enough for 4096
+// chains, at least 4, at most 2 GB of spins), time a step of one heat-bath
+// and min(L, 32) overrelaxation sweeps (best of two, after a warm-up step)
+// of every applicable mapping with its heuristic tile shape, then of the
+// fastest mapping with neighbouring tile shapes: site lanes with half and
+// twice the chains per workgroup, chain lanes with half and twice the waves
+// per packed row and the y-strips half and twice as tall.  The fastest plan
+// is kept.  The step is long enough for the chain-lane order to pay for its
+// first, cold pass through the cache.  Bimodal samples are timed in their
+// byte coding.  Results are cached per (device, L, n_temps, n_replicas,
+// samples timed, graphs, bimodal) for the process, and in the file
+// PTSG_PLAN_CACHE names when it is set.
+static pt_status autotuned_tiles(const pt_batch_desc *d, std::vector<Tile> &tiles)
 {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int, int, int, bool, bool>, int> cache;
+    static std::map<std::tuple<int, int, int, int, int, bool, bool>, Tile> cache;
     const unsigned graphs = d->flags & PT_F_GRAPHS;
     const unsigned bimodal = d->flags & PT_F_BIMODAL;
     int dev = 0;
@@ -1081,7 +1101,7 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
     PT_HIP(hipGetDeviceProperties(&prop, dev));
     std::string arch(prop.gcnArchName);
     std::replace(arch.begin(), arch.end(), ' ', '_');
-    mapping.assign(d->n_samples, kSiteLanes);
+    tiles.assign(d->n_samples, Tile{kSiteLanes, 0, 0, -1});
     std::map<std::pair<int, int>, std::vector<int>> classes;
     for (int s = 0; s < d->n_samples; ++s) classes[{d->L[s], d->n_temps[s]}].push_back(s);
     for (auto &cl : classes) {
@@ -1096,14 +1116,20 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
         const auto key = std::make_tuple(dev, L, cl.first.second, d->n_replicas, n, graphs != 0, bimodal != 0);
         const PlanKey pkey{arch, prop.multiProcessorCount, L, cl.first.second, d->n_replicas, n,
                            graphs != 0, bimodal != 0};
-        int best = L > 128 ? kSiteLanes : -1;  // the only mapping beyond L = 128
+        Tile best;
+        bool have = false;
         {
             std::lock_guard<std::mutex> lock(mu);
             auto it = cache.find(key);
-            if (it != cache.end()) best = it->second;
-            if (best < 0 && (best = plan_cache_lookup(pkey)) >= 0) cache[key] = best;
+            if (it != cache.end()) {
+                best = it->second;
+                have = true;
+            } else if (plan_cache_lookup(pkey, best)) {
+                cache[key] = best;
+                have = true;
+            }
         }
-        if (best < 0) {
+        if (!have) {
             std::vector<int> Ls(n, L), Ts(n, cl.first.second);
             std::vector<const double *> temps;
             std::vector<const float *> cpl;
@@ -1111,11 +1137,8 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
                 temps.push_back(d->temps[cl.second[q]]);
                 cpl.push_back(d->couplings[cl.second[q]]);
             }
-            std::vector<std::pair<int, unsigned>> cands = {{kSiteLanes, PT_F_SITE_LANES}};
-            if (L <= 128) cands.push_back({kChainLanes, PT_F_CHAIN_LANES});
-            if (L <= kRsMaxL) cands.push_back({kResident, PT_F_RESIDENT});
-            double best_t = 0.0;
-            for (auto &cand : cands) {
+            // time one plan; `used` receives the tile shape the context ran
+            auto time_plan = [&](const Tile &plan, float &ms_out, Tile &used) -> pt_status {
                 pt_batch_desc t{};
                 t.n_samples = n;
                 t.L = Ls.data();
@@ -1124,10 +1147,14 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
                 t.couplings = cpl.data();
                 t.n_replicas = d->n_replicas;
                 t.seed = d->seed;
-                t.flags = cand.second | graphs | bimodal;
+                t.flags = graphs | bimodal;
+                const std::vector<Tile> forced(n, plan);
                 pt_ctx *tc = nullptr;
-                pt_status st = init_batch(&tc, &t, nullptr);
+                pt_status st = init_batch(&tc, &t, &forced);
                 if (st != PT_OK) return st;
+                const LatticeClass &k = tc->classes[0];
+                used = Tile{k.mapping, k.mapping == kSiteLanes ? k.G : 0, k.mapping == kChainLanes ? k.split : 0,
+                            k.mapping == kChainLanes ? k.strip : -1};
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 float ms = 0.0f, best_rep = 0.0f;
                 hipError_t he = hipEventCreate(&e0);
@@ -1143,14 +1170,51 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
                         if (he == hipSuccess && (rep == 0 || ms < best_rep)) best_rep = ms;
                     }
                 }
-                ms = best_rep;
                 if (e0) (void)hipEventDestroy(e0);
                 if (e1) (void)hipEventDestroy(e1);
                 pt_free(tc);
                 if (st != PT_OK) return st;
                 if (he != hipSuccess) return fail(PT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(he));
-                if (best < 0 || ms < best_t) {
-                    best = cand.first;
+                ms_out = best_rep;
+                return PT_OK;
+            };
+            double best_t = 0.0;
+            std::vector<int> maps = {kSiteLanes};
+            if (L <= 128) maps.push_back(kChainLanes);
+            if (L <= kRsMaxL) maps.push_back(kResident);
+            for (int m : maps) {
+                float ms = 0.0f;
+                Tile used;
+                pt_status st = time_plan(Tile{m, 0, 0, -1}, ms, used);
+                if (st != PT_OK) return st;
+                if (!have || ms < best_t) {
+                    best = used;
+                    best_t = ms;
+                    have = true;
+                }
+            }
+            // neighbouring tile shapes of the fastest mapping
+            std::vector<Tile> shapes;
+            const int Cn = static_cast<int>(C);
+            if (best.mapping == kSiteLanes) {
+                for (int G : {best.G / 2, best.G * 2})
+                    if (G >= 1 && G <= std::min(Cn, kMaxGroup) && G != best.G) shapes.push_back(Tile{kSiteLanes, G, 0, -1});
+            } else if (best.mapping == kChainLanes) {
+                const int Lh = L / 2;
+                for (int sp : {best.split / 2, best.split * 2})
+                    if (sp >= 1 && sp <= 8 && Lh % sp == 0 && Lh / sp >= 2)
+                        shapes.push_back(Tile{kChainLanes, 0, sp, best.strip});
+                for (int sr : {best.strip / 2, best.strip * 2})
+                    if (best.strip > 0 && sr >= 2 && sr <= L && L % sr == 0 && sr != best.strip)
+                        shapes.push_back(Tile{kChainLanes, 0, best.split, sr});
+            }
+            for (const Tile &shape : shapes) {
+                float ms = 0.0f;
+                Tile used;
+                pt_status st = time_plan(shape, ms, used);
+                if (st != PT_OK) return st;
+                if (ms < best_t) {
+                    best = used;
                     best_t = ms;
                 }
             }
@@ -1158,9 +1222,23 @@ static pt_status autotuned_mappings(const pt_batch_desc *d, std::vector<int> &ma
             cache[key] = best;
             plan_cache_store(pkey, best);
         }
-        for (int s : cl.second) mapping[s] = best;
+        for (int s : cl.second) tiles[s] = best;
     }
     return PT_OK;
+}
+
+pt_status pt_get_tile(pt_ctx *c, int sample, int *chains_per_group, int *split, int *strip)
+{
+    if (!c) return fail(PT_ESTATE, "context is NULL (call pt_init first)");
+    if (sample < 0 || sample >= c->plan.S) return fail(PT_EINVAL, "sample out of range");
+    for (const auto &k : c->classes)
+        if (std::find(k.samples.begin(), k.samples.end(), sample) != k.samples.end()) {
+            if (chains_per_group) *chains_per_group = k.mapping == kSiteLanes ? k.G : k.mapping == kChainLanes ? 64 : 1;
+            if (split) *split = k.mapping == kChainLanes ? k.split : 0;
+            if (strip) *strip = k.mapping == kChainLanes ? k.strip : 0;
+            return PT_OK;
+        }
+    return fail(PT_EINVAL, "sample has no class");
 }
 
 pt_status pt_get_mapping(pt_ctx *c, int sample, unsigned *flag)
@@ -1187,15 +1265,17 @@ pt_status pt_init(pt_ctx **ctx, int L, const float *couplings, const double *tem
     return pt_init_batch(ctx, &d);
 }
 
-// Queue one step on `st`: every class's sweeps, then advance the device
-// heat-bath counter.
+// Queue one step on `st`: every class's sweeps (n_or == PT_OR_L: L
+// overrelaxation sweeps for a class of linear size L), then advance the
+// device heat-bath counter.
 static pt_status queue_step(pt_ctx *c, int n_hb, int n_or)
 {
-    std::vector<int> kinds(n_hb, kHeatbath);
-    kinds.insert(kinds.end(), n_or, kOverrelax);
     pt_status st;
-    for (const auto &k : c->classes)
+    for (const auto &k : c->classes) {
+        std::vector<int> kinds(n_hb, kHeatbath);
+        kinds.insert(kinds.end(), n_or == PT_OR_L ? k.L : n_or, kOverrelax);
         if ((st = sweep_class(c, k, kinds)) != PT_OK) return st;
+    }
     if (n_hb > 0) PT_HIP(launch_advance_counters(c->counters, static_cast<uint32_t>(n_hb), 0u, c->stream));
     return PT_OK;
 }
@@ -1204,8 +1284,9 @@ pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
 {
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
-    if (n_hb < 0 || n_or < 0) return fail(PT_EINVAL, "n_hb and n_or must be >= 0");
-    if (n_hb + n_or == 0) return PT_OK;
+    if (n_hb < 0 || (n_or < 0 && n_or != PT_OR_L))
+        return fail(PT_EINVAL, "n_hb must be >= 0 and n_or >= 0 or PT_OR_L");
+    if (n_hb == 0 && n_or == 0) return PT_OK;
     if (!c->use_graphs || c->profiling) {
         if ((st = queue_step(c, n_hb, n_or)) != PT_OK) return st;
     } else {

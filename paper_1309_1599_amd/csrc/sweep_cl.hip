@@ -17,9 +17,14 @@
 // visited in strips of `strip` y-rows, z-major within a strip, so that the
 // y- and z-neighbour rows a wave reads were fetched into its XCD's L2 by
 // the waves of the rows just before it.
-// One chain group of an L = 64 sample is 201 MB and the sample's couplings
-// 28 MB: together they fit in the 256 MB Infinity Cache, which is why the
-// host runs all sweeps of one group back to back.
+// The host runs all sweeps of one chain group back to back so that the
+// group stays in the 256 MB Infinity Cache between half-sweeps.  At L = 64
+// a group is 201 MB of spins; a half-sweep also reads its colour's packed
+// couplings (28.3 MB, 216 bytes a site), so one half-sweep touches 229 MB
+// and a whole sweep, both colours' couplings, 258 MB: slightly more than
+// the cache.  (Reading each bond once from the 108-byte canonical blocks
+// would make a sweep fit, but the four scattered scalar loads per site
+// measured slower than the one contiguous 216-byte block.)
 #include "kernels.hpp"
 #include "philox.hpp"
 #include "spin_update.hpp"

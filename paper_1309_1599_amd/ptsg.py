@@ -19,6 +19,7 @@ PT_K_OVERRELAX, PT_K_HEATBATH, PT_K_RESIDENT = 0, 1, 2
 PT_F_SITE_LANES, PT_F_CHAIN_LANES, PT_F_RESIDENT, PT_F_GRAPHS, PT_F_PLAIN, PT_F_AUTOTUNE, PT_F_BIMODAL = \
     1, 2, 4, 8, 16, 32, 64
 PT_F_ROW_OR = 128
+PT_OR_L = -1   # pt_step: L overrelaxation sweeps for a sample of linear size L
 
 # numpy view of the C struct pt_meas (744 bytes, no padding)
 MEAS_DTYPE = np.dtype([
@@ -34,7 +35,7 @@ assert MEAS_DTYPE.itemsize == 744
 EXPORTS = ["pt_init", "pt_workspace_size", "pt_init_batch", "pt_step", "pt_swap", "pt_measure",
            "pt_measure_noalloc",
            "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_perms", "pt_get_energy", "pt_get_counters",
-           "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping",
+           "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping", "pt_get_tile",
            "pt_save", "pt_load", "pt_free", "pt_last_error"]
 
 
@@ -90,6 +91,7 @@ def load_library(path=LIB_PATH):
         "pt_profile": (i, [vp, i]),
         "pt_kernel_time": (i, [vp, i, C.POINTER(u64), C.POINTER(C.c_double)]),
         "pt_get_mapping": (i, [vp, i, C.POINTER(C.c_uint)]),
+        "pt_get_tile": (i, [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "pt_save": (i, [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]),
         "pt_load": (i, [vp, vp, C.c_size_t]),
         "pt_free": (None, [vp]),
@@ -297,6 +299,13 @@ def pt_get_mapping(ctx, sample):
     f = C.c_uint()
     _check(load_library().pt_get_mapping(ctx.ptr, int(sample), C.byref(f)))
     return f.value
+
+
+def pt_get_tile(ctx, sample):
+    """(chains per workgroup, waves per packed row, y-rows per strip) of a sample's sweeps."""
+    g, sp, sr = C.c_int(), C.c_int(), C.c_int()
+    _check(load_library().pt_get_tile(ctx.ptr, int(sample), C.byref(g), C.byref(sp), C.byref(sr)))
+    return g.value, sp.value, sr.value
 
 
 def pt_save(ctx):

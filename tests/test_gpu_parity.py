@@ -359,3 +359,30 @@ def test_default_mapping_reported():
         with pytest.raises(ptsg.PtError):
             ptsg.pt_get_mapping(ctx, len(Ls))
         ptsg.pt_free(ctx)
+
+
+@pytest.mark.parametrize("Ls", [[12, 8], [8, 12]], ids=["L12-first", "L8-first"])
+def test_step_with_L_overrelaxation_sweeps_per_sample(Ls):
+    """pt_step(n_hb, PT_OR_L), the paper's Monte Carlo step (Sec. III) in a
+    batch of two sizes: sample 0 takes exactly the sweeps of a context of
+    that sample alone stepped with n_or = L, bit for bit (same sample index,
+    so the same random numbers), through three steps and tempering passes."""
+    T, R, seed = 6, 2, 911
+    temps = [inputs.geometric_temps(0.6, 1.6, T)] * 2
+    cpl = [inputs.gaussian_couplings(L, seed, s) for s, L in enumerate(Ls)]
+    both = ptsg.pt_init_batch(Ls, cpl, temps, R, seed)
+    alone = ptsg.pt_init_batch(Ls[:1], cpl[:1], temps[:1], R, seed)
+    for _ in range(3):
+        ptsg.pt_step(both, 1, ptsg.PT_OR_L)
+        ptsg.pt_swap(both)
+        ptsg.pt_step(alone, 1, Ls[0])
+        ptsg.pt_swap(alone)
+    for r in range(R):
+        np.testing.assert_array_equal(ptsg.pt_get_perm(both, 0, r), ptsg.pt_get_perm(alone, 0, r))
+        for k in range(T):
+            np.testing.assert_array_equal(ptsg.pt_get_spins(both, 0, r, k), ptsg.pt_get_spins(alone, 0, r, k))
+    np.testing.assert_allclose(ptsg.pt_get_energy(both)[0], ptsg.pt_get_energy(alone)[0], rtol=1e-13)
+    with pytest.raises(ptsg.PtError):
+        ptsg.pt_step(both, 1, -2)
+    ptsg.pt_free(both)
+    ptsg.pt_free(alone)
