@@ -112,16 +112,17 @@ int cl_batch(int L, int n_items)
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_items, kCacheBudget / item)));
 }
 
-// Segments per packed row: the most segments that keep at least 8 sites per
-// wave (at L = 64 four segments of 8 sites measured 14% faster than whole
-// rows: twice the waves in flight to cover the memory latency), then more
-// while a launch would have fewer than 1024 workgroups.
+// Segments per packed row: the most segments (up to 8) that keep at least 4
+// sites per wave (at L = 64 eight segments of 4 sites measured 6% faster
+// than four of 8, and those 14% faster than whole rows: more waves in
+// flight to cover the memory latency), then more while a launch would have
+// fewer than 1024 workgroups.
 int choose_split(int L, int batch)
 {
     const int Lh = L / 2;
     int best = 1;
     for (int s = 2; s <= 8; s *= 2)
-        if (Lh % s == 0 && Lh / s >= 8) best = s;
+        if (Lh % s == 0 && Lh / s >= 4) best = s;
     while (static_cast<int64_t>(cl_blocks(L, best)) * batch < 1024 && best < 8 && Lh % (2 * best) == 0 &&
            Lh / (2 * best) >= 2)
         best *= 2;
