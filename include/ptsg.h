@@ -120,7 +120,9 @@ typedef struct {
  *   back so that its working set stays in the 256 MB Infinity Cache;
  * resident: one workgroup per chain keeps the whole lattice in LDS for all
  *   sweeps of a step (L <= 16).
- * Automatic: resident for L <= 16; chain lanes for 24 <= L <= 64 (the
+ * Automatic: resident for L <= 8, and for L <= 16 when the lattice class
+ * (the samples of one L and number of temperatures) holds at least 256
+ * chains, enough workgroups for the chip; chain lanes for 24 <= L <= 64 (the
  * measured range where they are faster) when the sample's chains fill its
  * 64-lane waves to >= 90%; else site lanes.  A forced mapping that does not
  * apply to a sample (resident with L > 16, chain lanes with L > 128) falls

@@ -145,7 +145,14 @@ int choose_mapping(const pt_batch_desc *d, int s)
     if (d->flags & (PT_F_SITE_LANES | PT_F_PLAIN)) return kSiteLanes;
     if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
     if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
-    if (L <= kRsMaxL) return kResident;
+    // Resident lattices (one workgroup per chain) need enough chains to fill
+    // the chip: with 16 samples of L = 12 or 16 they beat both other mappings
+    // (18.7 and 14.1 ps/SU), with the 32 chains of one L = 16 sample they
+    // trail them (83 against 68 site lanes, 66 chain lanes).
+    int class_chains = 0;
+    for (int q = 0; q < d->n_samples; ++q)
+        if (d->L[q] == L && d->n_temps[q] == d->n_temps[s]) class_chains += C;
+    if (L <= 8 || (L <= kRsMaxL && class_chains >= 256)) return kResident;
     // Chain lanes only when the 64-lane waves are (nearly) full and L is in
     // the measured range where they win: site lanes are faster at L = 20
     // and at L = 96 and 128, chain lanes from L = 24 to 64 (up to there a

@@ -347,12 +347,16 @@ def test_autotune_picks_valid_mapping_and_matches_forced():
 
 
 def test_default_mapping_reported():
-    """The automatic choice: resident up to L = 16; chain lanes for
-    24 <= L <= 64 with (nearly) full 64-lane waves; site lanes otherwise."""
+    """The automatic choice: resident at L <= 8, and up to L = 16 when the
+    class holds at least 256 chains; chain lanes for 24 <= L <= 64 with
+    (nearly) full 64-lane waves; site lanes otherwise."""
     t32 = inputs.geometric_temps(0.6, 1.6, 32)
+    t16 = inputs.geometric_temps(0.6, 1.6, 16)
     cases = [([8, 24], [[1.0, 2.0]] * 2, [ptsg.PT_F_RESIDENT, ptsg.PT_F_SITE_LANES]),  # 2 chains
              ([20, 24, 64, 96], [t32] * 4, [ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES,
-                                            ptsg.PT_F_CHAIN_LANES, ptsg.PT_F_SITE_LANES])]
+                                            ptsg.PT_F_CHAIN_LANES, ptsg.PT_F_SITE_LANES]),
+             ([16], [t16], [ptsg.PT_F_SITE_LANES]),                        # 32 chains of L = 16
+             ([16] * 8, [t16] * 8, [ptsg.PT_F_RESIDENT] * 8)]               # 256 chains
     for Ls, temps, want in cases:
         ctx, _ = _ctx(Ls, temps, 2, 920, cpl=[np.zeros((3, L ** 3, 3, 3), np.float32) for L in Ls])
         assert [ptsg.pt_get_mapping(ctx, s) for s in range(len(Ls))] == want
