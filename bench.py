@@ -72,12 +72,12 @@ def cpu_model():
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
+def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12, per_thread=16):
     """The FP64 oracle as it stands on a bounded sample of the same workload:
     chains of sample 0, each one heat-bath sweep, n_or overrelaxation sweeps
     and one energy evaluation; the per-spin-update time is composed with the
     real step's weights.  Timed single-threaded (n_chains chains) and with
-    one thread per host core of this GPU's share (at most 16), sixteen
+    one thread per host core of this GPU's share (at most 16), `per_thread`
     chains per thread (the oracle's C calls release the GIL)."""
     import concurrent.futures as cf
     import oracle as O
@@ -104,7 +104,7 @@ def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
 
     single, busy1 = composed([chain(c) for c in range(n_chains)], n_chains)
     workers = max(1, min(16, os.cpu_count() or 1))
-    n_mt = 16 * workers
+    n_mt = per_thread * workers
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(workers) as ex:
         times = list(ex.map(chain, range(n_mt)))
@@ -123,6 +123,42 @@ def cpu_baseline(L, cpl, temps, seed, n_hb, n_or_step, n_chains=64, n_or=12):
                   f"{n_or} overrelaxation sweeps and one energy, composed to the {n_hb} HB + "
                   f"{n_or_step} OR step: {n_mt} chains on {workers} threads ({wall:.1f} s wall, "
                   f"{busy:.1f} thread-s); single-threaded {n_chains} chains ({busy1:.1f} s)",
+    }
+
+
+def mixed_cpu_baseline(Ls, cpl, temps, R, seed, n_hb, n_or, or_l):
+    """The oracle's ps/SU on a batch of several L: one bounded sample per
+    distinct L (the first sample of that L, 16 chains single-threaded and
+    four chains a thread), composed with each L's share of the step's spin
+    updates, so that it is the time the oracle would take for the whole
+    batch divided by its spin updates."""
+    parts, su, per_L = [], {}, {}
+    for Lv, t in zip(Ls, temps):
+        su[Lv] = su.get(Lv, 0) + (n_hb + (Lv if n_or == or_l else n_or)) * R * len(t) * Lv ** 3
+    tot = sum(su.values())
+    value = single = 0.0
+    for Lv in sorted(su):
+        i = Ls.index(Lv)
+        b = cpu_baseline(Lv, cpl[i], temps[i], seed, n_hb, Lv if n_or == or_l else n_or,
+                         n_chains=16, per_thread=4)
+        w = su[Lv] / tot
+        value += w * b["value"]
+        single += w * b["single_thread_value"]
+        per_L[str(Lv)] = {"value": b["value"], "single_thread_value": b["single_thread_value"],
+                          "su_share": round(w, 4)}
+        parts.append(b)
+    return {
+        "value": round(value, 1),
+        "unit": "ps/SU",
+        "cores": parts[0]["cores"],
+        "kind": "oracle",
+        "cpu_model": parts[0]["cpu_model"],
+        "single_thread_value": round(single, 1),
+        "per_L": per_L,
+        "sample": "per L, chains on the couplings of the first sample of that L, each 1 heat-bath + 12 "
+                  "overrelaxation sweeps and one energy, composed to that L's step (1 HB + L OR); the "
+                  "per-L figures weighted by each L's share of the step's spin updates: "
+                  + "; ".join(f"L={Lv}: {b['sample'].split(': ', 1)[1]}" for Lv, b in zip(sorted(su), parts)),
     }
 
 
@@ -340,8 +376,10 @@ def main():
                                         "speedup_of_value": round(plain / ps_per_su, 3),
                                         "form": "site lanes, one chain per workgroup (couplings "
                                                 "re-read by every chain), same step"}
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(L, cpl[0], temps[0], seed, n_hb, L if n_or == ptsg.PT_OR_L else n_or)
+    if not args.no_cpu_baseline and not mixed:
+        result["cpu_baseline"] = cpu_baseline(L, cpl[0], temps[0], seed, n_hb, n_or)
+    elif not args.no_cpu_baseline:
+        result["cpu_baseline"] = mixed_cpu_baseline(Ls, cpl, temps, R, seed, n_hb, n_or, ptsg.PT_OR_L)
     print(json.dumps(result), flush=True)
 
 
