@@ -197,7 +197,8 @@ def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, w
             step(t)
         ptsg.pt_sync(ctx)
         kt = {k: ptsg.pt_kernel_time(ctx, v) for k, v in
-              (("or", ptsg.PT_K_OVERRELAX), ("hb", ptsg.PT_K_HEATBATH), ("rs", ptsg.PT_K_RESIDENT))}
+              (("or", ptsg.PT_K_OVERRELAX), ("hb", ptsg.PT_K_HEATBATH), ("rs", ptsg.PT_K_RESIDENT),
+               ("ps", ptsg.PT_K_PERSISTENT))}
         ptsg.pt_profile(ctx, False)
     ptsg.pt_free(ctx)
     del ctx
@@ -223,6 +224,11 @@ def main():
                     help="gaussian: 9 iid N(0,1) entries per bond (the workload); bimodal: the paper's "
                          "family J*1 + D_sym, J = +-1, D_ab = +-0.5, stored as one byte per bond "
                          "(PT_F_BIMODAL) where the mapping allows")
+    ap.add_argument("--persistent", action="store_true",
+                    help="time the persistent step (PT_F_PERSISTENT: one cooperative launch per step) "
+                         "as the headline instead of the captured multi-launch step")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent-step figure reported beside the headline")
     ap.add_argument("--or-order", choices=("checkerboard", "rows"), default="checkerboard",
                     help="rows: overrelaxation in the row order (PT_F_ROW_OR, chain-lane mapping)")
     args = ap.parse_args()
@@ -253,6 +259,8 @@ def main():
     if bimodal:
         flags |= ptsg.PT_F_BIMODAL
     rows = args.or_order == "rows"
+    if args.persistent:
+        flags = (flags & ~(ptsg.PT_F_RESIDENT | ptsg.PT_F_AUTOTUNE | ptsg.PT_F_GRAPHS)) | ptsg.PT_F_PERSISTENT
     if rows:
         flags = (flags & ~(ptsg.PT_F_SITE_LANES | ptsg.PT_F_RESIDENT | ptsg.PT_F_AUTOTUNE)) | ptsg.PT_F_ROW_OR
     L = Ls[0]
@@ -270,7 +278,20 @@ def main():
     ps_per_su = wall / (args.steps * su_per_step) * 1e12
     n_chains = sum(R * len(t) for t in temps)
 
-    if not mixed and mapping != "resident":
+    if args.persistent and not mixed:
+        # the whole step is one launch: its algorithmic bytes (24 + 108/C
+        # per spin update, or 24 + 3/C with byte couplings) over its duration
+        n_l, ms = kt["ps"]
+        bytes_per_su = 24.0 + (3.0 if bimodal else 108.0) / C
+        avg_s = ms / max(1, n_l) / 1e3
+        achieved = bytes_per_su * su_per_step / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": "cl_step_kernel" if mapping == "chain" else "site_step_kernel",
+                "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "algorithmic_bytes_per_launch": bytes_per_su * su_per_step,
+                "bytes_per_su": round(bytes_per_su, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
+                "launches": n_l}
+    elif not mixed and mapping != "resident":
         # HBM roofline of the overrelaxation half-sweep: per spin update the
         # method must read and write the spin (24 B) and read the couplings
         # of the site (108 B as floats, 3 B as bimodal codes), which the C
@@ -333,7 +354,8 @@ def main():
                         {str(Lv): maps[Ls.index(Lv)] + " lanes" for Lv in sorted(set(Ls))}),
             "mapping_choice": args.mapping,
             "overrelaxation_order": args.or_order,
-            "graphs": not args.no_graphs,
+            "graphs": not args.no_graphs and not args.persistent,
+            "step_launch": "persistent" if args.persistent else "multi-launch",
         },
         "roofline": roof,
     }
@@ -342,9 +364,18 @@ def main():
     if kt is not None:
         # device time of the sweep kernels alone (no swap, energy finalise,
         # measurement or launch gaps), per spin update
-        sweep_ms = kt["or"][1] + kt["hb"][1] + kt["rs"][1]
+        sweep_ms = kt["or"][1] + kt["hb"][1] + kt["rs"][1] + kt["ps"][1]
         result["sweep_kernels_ps_per_su"] = round(sweep_ms * 1e-3 / (args.steps * su_per_step) * 1e12, 4)
 
+    if not args.persistent and not args.no_persistent and not rows:
+        # the same workload as one persistent launch per step
+        pf = (flags & ~(ptsg.PT_F_RESIDENT | ptsg.PT_F_AUTOTUNE | ptsg.PT_F_GRAPHS)) | ptsg.PT_F_PERSISTENT
+        w, su, _, m = run(ptsg, torch, Ls, cpl, temps, R, seed, pf, n_hb, n_or, every, args.steps, 1,
+                          timing=False)
+        ps = w / (args.steps * su) * 1e12
+        result["persistent_step"] = {"value": round(ps, 4), "unit": "ps/SU", "mapping": m[0] + " lanes",
+                                     "ratio_to_value": round(ps / ps_per_su, 3),
+                                     "form": "one cooperative launch per step (PT_F_PERSISTENT)"}
     if mixed:
         # each L alone in its own context (per-lattice launches) beside the mixed batch
         per_L = {}

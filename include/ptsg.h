@@ -175,7 +175,23 @@ enum {
      * touch across the boundary, in one class), L <= 128, and runs on the
      * chain-lane mapping (excludes PT_F_SITE_LANES, PT_F_RESIDENT,
      * PT_F_PLAIN). */
-    PT_F_ROW_OR = 128u
+    PT_F_ROW_OR = 128u,
+    /* Persistent step (App. A.3: all lattices of the batch updated by one
+     * program): pt_step runs as ONE cooperative kernel launch that performs
+     * every half-sweep of every sample and L class, then the energies, with a
+     * grid-wide barrier between dependent half-sweeps (the launches the
+     * multi-launch path makes become descriptors of a device work list; the
+     * half-sweeps of different classes share a phase).  The grid is what the
+     * device keeps resident (the launch fails with PT_EDEVICE otherwise).
+     * Results are bit-identical to the multi-launch path with the same
+     * mapping and tile shape.  One mapping serves the whole batch: chain
+     * lanes when PT_F_CHAIN_LANES is set (and every L <= 128) or, with no
+     * mapping flag, when they pay for every sample (24 <= L <= 64 and
+     * >= 90% wave fill); else site lanes.  Excludes PT_F_RESIDENT and
+     * PT_F_ROW_OR; PT_F_GRAPHS and PT_F_AUTOTUNE are ignored.  The work list
+     * of each (n_hb, n_or) is built on its first use, in device memory the
+     * library allocates even when the caller provides the workspace. */
+    PT_F_PERSISTENT = 256u
 };
 
 /* The mapping used for a sample: PT_F_SITE_LANES, PT_F_CHAIN_LANES or
@@ -288,7 +304,8 @@ pt_status pt_sync(pt_ctx *ctx);
  * HIP events on the context's stream; pt_kernel_time synchronises and
  * returns, for one kernel kind, the number of launches and their summed
  * device time since profiling was (re-)enabled. */
-enum { PT_K_OVERRELAX = 0, PT_K_HEATBATH = 1, PT_K_RESIDENT = 2 /* whole-step launches */ };
+enum { PT_K_OVERRELAX = 0, PT_K_HEATBATH = 1, PT_K_RESIDENT = 2 /* whole-step launches */,
+       PT_K_PERSISTENT = 3 /* PT_F_PERSISTENT step launches (timed by events around the launch) */ };
 pt_status pt_profile(pt_ctx *ctx, int enable);
 pt_status pt_kernel_time(pt_ctx *ctx, int kind, uint64_t *launches, double *ms);
 

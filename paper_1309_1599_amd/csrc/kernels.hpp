@@ -30,6 +30,7 @@
 
 namespace ptsg {
 
+constexpr int kXcds = 8;           // XCDs of the chip, each with its own L2
 constexpr int kSweepBlock = 256;   // threads per sweep workgroup (4 waves)
 constexpr int kMaxGroup = 128;     // chains per sweep workgroup (upper bound)
 constexpr int kMeasBlock = 256;
@@ -153,6 +154,34 @@ struct MeasParams {
     int rec0;                    // first record of a launch (blockIdx.x is relative)
 };
 
+// Persistent step: one cooperative launch runs the half-sweeps (and energy
+// finalisations) of a whole step.  Every launch the multi-launch path would
+// make becomes a descriptor of the same parameters and grid; descriptors
+// whose launches may run concurrently form a phase, and the workgroups of
+// the persistent grid meet at a grid-wide barrier after each phase.  Within
+// a phase, virtual block v of the concatenated grids is taken by workgroup
+// v mod gridDim.x; its (x, y, z) in the descriptor's grid is x fastest.
+enum StepOp { kOpSite = 0, kOpChain = 1, kOpFinalize = 2 };
+
+struct StepDesc {
+    int op, kind, energy;        // body (StepOp), sweep kind, fused energy partials
+    int gx, gy, gz, n_blocks;    // grid of the launch it stands for (gx a multiple of 8)
+    union {
+        SweepParams sp;
+        ClParams cp;
+        EnergyParams ep;
+    };
+};
+
+struct PersistParams {
+    const StepDesc *desc;        // every descriptor, phase by phase
+    const int *phase_first;      // [n_phases]: first descriptor of each phase
+    const int *phase_blocks;     // [n_phases]: virtual blocks of each phase
+    int n_phases;
+    uint32_t *counters;          // [0] += d_hb by one lane once every phase is done
+    uint32_t d_hb;
+};
+
 // Optional kernel timing: when `start` is set, the dispatch itself stamps the
 // two events at the kernel's start and end (the time a profiler reports).
 struct LaunchTiming {
@@ -189,6 +218,13 @@ hipError_t launch_advance_counters(uint32_t *counters, uint32_t d_hb, uint32_t d
 hipError_t launch_init_spins(float *spins, int64_t spin_base, int lanes, int L, int C, int T,
                              int sample, uint32_t key0, uint32_t key1, hipStream_t st);
 int cl_blocks(int L, int split);
+// Persistent step launches (cooperative: every workgroup of the grid is
+// resident at once, or the launch fails).  `grid` must be a multiple of 8
+// and at most the CU count times the *_step_blocks_per_cu() figure.
+int site_step_blocks_per_cu();
+int cl_step_blocks_per_cu();
+hipError_t launch_site_step(const PersistParams &p, int grid, hipStream_t st);
+hipError_t launch_cl_step(const PersistParams &p, int grid, hipStream_t st);
 hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, float *canon,
                            bool to_canon, hipStream_t st);
 // Plane kernels for records [rec0, rec0 + n) (lattices up to L), then, once

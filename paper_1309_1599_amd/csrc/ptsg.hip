@@ -138,10 +138,31 @@ int choose_strip(int L)
     return 0;
 }
 
+// Chain lanes where they are measured faster: 24 <= L <= 64 with the
+// sample's chains filling its 64-lane waves to >= 90%.
+bool chain_lanes_pay(int L, int C)
+{
+    const int waves = (C + 63) / 64;
+    return L >= 24 && L <= 64 && 10 * C >= 9 * 64 * waves;
+}
+
+// A persistent step is one kernel, so one mapping serves the whole batch:
+// chain lanes when forced (and every L <= 128) or when they pay for every
+// sample, else site lanes.
+int persistent_mapping(const pt_batch_desc *d)
+{
+    bool chain = !(d->flags & (PT_F_SITE_LANES | PT_F_PLAIN));
+    for (int q = 0; q < d->n_samples && chain; ++q)
+        chain = (d->flags & PT_F_CHAIN_LANES) ? d->L[q] <= 128
+                                              : chain_lanes_pay(d->L[q], d->n_replicas * d->n_temps[q]);
+    return chain ? kChainLanes : kSiteLanes;
+}
+
 int choose_mapping(const pt_batch_desc *d, int s)
 {
     const int L = d->L[s], C = d->n_replicas * d->n_temps[s];
     if (d->flags & PT_F_ROW_OR) return kChainLanes;  // the row-order kernel is chain-lane
+    if (d->flags & PT_F_PERSISTENT) return persistent_mapping(d);
     if (d->flags & (PT_F_SITE_LANES | PT_F_PLAIN)) return kSiteLanes;
     if (d->flags & PT_F_CHAIN_LANES) return L <= 128 ? kChainLanes : kSiteLanes;
     if (d->flags & PT_F_RESIDENT) return L <= kRsMaxL ? kResident : kSiteLanes;
@@ -159,8 +180,7 @@ int choose_mapping(const pt_batch_desc *d, int s)
     // group of 64 chains, 201 MB at L = 64, stays in the 256 MB Infinity
     // Cache between the half-sweeps that the group-major order runs back to
     // back).
-    const int waves = (C + 63) / 64;
-    return (L >= 24 && L <= 64 && 10 * C >= 9 * 64 * waves) ? kChainLanes : kSiteLanes;
+    return chain_lanes_pay(L, C) ? kChainLanes : kSiteLanes;
 }
 
 // The paper's coupling family (Sec. II.A): M = J*1 + D_sym with J = +-1 and
@@ -219,6 +239,9 @@ std::string validate(const pt_batch_desc *d)
     if (!d->L || !d->n_temps || !d->temps || !d->couplings) return "NULL array in descriptor";
     if ((d->flags & PT_F_ROW_OR) && (d->flags & (PT_F_SITE_LANES | PT_F_RESIDENT | PT_F_PLAIN)))
         return "PT_F_ROW_OR runs on the chain-lane mapping: it excludes PT_F_SITE_LANES, PT_F_RESIDENT and PT_F_PLAIN";
+    if ((d->flags & PT_F_PERSISTENT) && (d->flags & (PT_F_ROW_OR | PT_F_RESIDENT)))
+        return "PT_F_PERSISTENT runs the checkerboard site-lane or chain-lane sweeps: it excludes PT_F_ROW_OR "
+               "and PT_F_RESIDENT";
     if (d->n_replicas < 1 || d->n_replicas > 256) return "n_replicas must be in [1, 256]";
     for (int s = 0; s < d->n_samples; ++s) {
         const int L = d->L[s];
@@ -399,6 +422,17 @@ struct pt_ctx {
     bool row_or = false;              // PT_F_ROW_OR: overrelaxation sweeps in the row order
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
+    // PT_F_PERSISTENT: one program per (n_hb, n_or), in library-owned memory
+    struct Program {
+        std::vector<StepDesc> desc;
+        std::vector<int> first, blocks;   // per phase
+        char *mem = nullptr;              // device copies of desc, first, blocks
+        const StepDesc *d_desc = nullptr;
+        const int *d_first = nullptr, *d_blocks = nullptr;
+        int grid = 0;
+    };
+    bool persistent = false;
+    std::map<std::pair<int, int>, Program> programs;
     int *d_L = nullptr, *d_T = nullptr, *d_chain_base = nullptr, *d_perm_base = nullptr,
         *d_beta_base = nullptr, *d_twid_base = nullptr, *d_lanes = nullptr;
     int64_t *d_spin_base = nullptr, *d_cpls_base = nullptr, *d_cpl6_base = nullptr;
@@ -406,8 +440,8 @@ struct pt_ctx {
     bool profiling = false;
     std::vector<std::pair<int, Event>> pending;
     std::vector<Event> free_events;
-    uint64_t prof_launches[3] = {0, 0, 0};
-    double prof_ms[3] = {0.0, 0.0, 0.0};
+    uint64_t prof_launches[4] = {0, 0, 0, 0};
+    double prof_ms[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
 namespace {
@@ -525,7 +559,7 @@ pt_status timed_launch(pt_ctx *c, int kind, Launch launch)
     return PT_OK;
 }
 
-pt_status finalize_energies(pt_ctx *c, const LatticeClass &k)
+EnergyParams energy_params(pt_ctx *c, const LatticeClass &k)
 {
     EnergyParams e{};
     e.e_part = c->epart;
@@ -535,13 +569,84 @@ pt_status finalize_energies(pt_ctx *c, const LatticeClass &k)
     e.chain_base = c->d_chain_base;
     e.C = k.C;
     e.E = c->E;
-    PT_HIP(launch_energy_finalize(e, static_cast<int>(k.samples.size()), c->stream));
+    return e;
+}
+
+pt_status finalize_energies(pt_ctx *c, const LatticeClass &k)
+{
+    PT_HIP(launch_energy_finalize(energy_params(c, k), static_cast<int>(k.samples.size()), c->stream));
     return PT_OK;
 }
 
-// The sweeps of one class: `kinds` lists the sweep kinds in order; the n-th
-// heat-bath sweep of the list uses Philox counter (device heat-bath count) + n.
-// The energy partials are fused into the last half-sweep.
+// The launches of one site-lane or chain-lane class's checkerboard sweeps,
+// in order, as descriptors (the last one finalises the energies).  `kinds`
+// lists the sweep kinds in order; the n-th heat-bath sweep of the list uses
+// Philox counter (device heat-bath count) + n, and the energy partials are
+// fused into the last half-sweep.  A descriptor may depend on the ones
+// before it, never on a later one.
+std::vector<StepDesc> class_sequence(pt_ctx *c, const LatticeClass &k, const std::vector<int> &kinds)
+{
+    std::vector<StepDesc> seq;
+    const int total = static_cast<int>(kinds.size());
+    const bool site = k.lanes == 1;
+    // site lanes: sample-batch-major; chain lanes: chain-group-major -- every
+    // sweep of one batch before the next
+    const int n_units = site ? static_cast<int>(k.samples.size()) : static_cast<int>(k.items.size() / 2);
+    for (int first = 0; first < n_units; first += k.batch) {
+        const int cnt = std::min(k.batch, n_units - first);
+        uint32_t hb = 0;
+        for (int n = 0; n < total; ++n) {
+            for (int colour = 0; colour < 2; ++colour) {
+                StepDesc D{};
+                D.kind = kinds[n];
+                D.energy = n == total - 1 && colour == 1;
+                if (site) {
+                    D.op = kOpSite;
+                    D.sp = sweep_params(c, k, colour, hb);
+                    D.sp.samples = k.d_samples + first;
+                    D.gx = kXcds * D.sp.per;
+                    D.gy = (k.C + k.G - 1) / k.G;
+                } else {
+                    D.op = kOpChain;
+                    D.cp = cl_params(c, k, first, colour, hb);
+                    D.gx = kXcds * D.cp.per;
+                    D.gy = 1;
+                }
+                D.gz = cnt;
+                D.n_blocks = D.gx * D.gy * D.gz;
+                seq.push_back(D);
+            }
+            if (kinds[n] == kHeatbath) ++hb;
+        }
+    }
+    StepDesc F{};
+    F.op = kOpFinalize;
+    F.ep = energy_params(c, k);
+    F.gx = ((k.C + 3) / 4 + kXcds - 1) / kXcds * kXcds;   // a multiple of 8; waves past C return
+    F.gy = static_cast<int>(k.samples.size());
+    F.gz = 1;
+    F.n_blocks = F.gx * F.gy;
+    seq.push_back(F);
+    return seq;
+}
+
+// One descriptor as its own kernel launch.
+pt_status launch_desc(pt_ctx *c, const StepDesc &D)
+{
+    if (D.op == kOpSite)
+        return timed_launch(c, D.kind, [&](const LaunchTiming &t) {
+            return launch_half_sweep(D.kind, D.energy, D.sp, D.gz, c->stream, t);
+        });
+    if (D.op == kOpChain)
+        return timed_launch(c, D.kind, [&](const LaunchTiming &t) {
+            return launch_cl_half_sweep(D.kind, D.energy, D.cp, D.gz, c->stream, t);
+        });
+    PT_HIP(launch_energy_finalize(D.ep, D.gy, c->stream));
+    return PT_OK;
+}
+
+// The sweeps of one class: `kinds` lists the sweep kinds in order (see
+// class_sequence).
 pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &kinds)
 {
     const int total = static_cast<int>(kinds.size());
@@ -573,64 +678,48 @@ pt_status sweep_class(pt_ctx *c, const LatticeClass &k, const std::vector<int> &
         return timed_launch(c, p.energy_only ? kEnergyOnly : kResidentKind,
                             [&](const LaunchTiming &t) { return launch_resident_step(p, n_chains, c->stream, t); });
     }
-    if (k.lanes == 1) {
-        // sample-batch-major: every sweep of one batch of samples before the next
-        const int n_samples = static_cast<int>(k.samples.size());
-        for (int first = 0; first < n_samples; first += k.batch) {
-            const int ns = std::min(k.batch, n_samples - first);
-            uint32_t hb = 0;
-            for (int n = 0; n < total; ++n) {
-                const int kind = kinds[n];
-                for (int colour = 0; colour < 2; ++colour) {
-                    const bool energy = n == total - 1 && colour == 1;
-                    SweepParams p = sweep_params(c, k, colour, hb);
-                    p.samples = k.d_samples + first;
+    if (k.lanes == 1 || !c->row_or) {
+        for (const StepDesc &D : class_sequence(c, k, kinds))
+            if ((st = launch_desc(c, D)) != PT_OK) return st;
+        return PT_OK;
+    }
+    // chain lanes with the row-ordered overrelaxation: chain-group-major,
+    // every sweep of one batch of items before the next
+    const int n_items = static_cast<int>(k.items.size() / 2);
+    for (int first = 0; first < n_items; first += k.batch) {
+        const int cnt = std::min(k.batch, n_items - first);
+        uint32_t hb = 0;
+        for (int n = 0; n < total; ++n) {
+            const int kind = kinds[n];
+            if (kind == kOverrelax) {
+                // class 0 rows, then class 1; energies after the last sweep
+                ClParams p = cl_params(c, k, first, 0, hb);
+                const int tiles = (row_waves(k.L) + kClWaves - 1) / kClWaves;
+                p.per = (tiles + 7) / 8;   // grid = 8 XCDs x per
+                for (int cls = 0; cls < 2; ++cls) {
                     st = timed_launch(c, kind, [&](const LaunchTiming &t) {
-                        return launch_half_sweep(kind, energy, p, ns, c->stream, t);
+                        return launch_cl_row_or(p, cls, cnt, c->stream, t);
                     });
                     if (st != PT_OK) return st;
                 }
-                if (kind == kHeatbath) ++hb;
-            }
-        }
-    } else {
-        // chain-group-major: every sweep of one batch of items before the next
-        const int n_items = static_cast<int>(k.items.size() / 2);
-        for (int first = 0; first < n_items; first += k.batch) {
-            const int cnt = std::min(k.batch, n_items - first);
-            uint32_t hb = 0;
-            for (int n = 0; n < total; ++n) {
-                const int kind = kinds[n];
-                if (kind == kOverrelax && c->row_or) {
-                    // row order: class 0 rows, then class 1; energies after the last sweep
-                    ClParams p = cl_params(c, k, first, 0, hb);
-                    const int tiles = (row_waves(k.L) + kClWaves - 1) / kClWaves;
-                    p.per = (tiles + 7) / 8;   // grid = 8 XCDs x per
-                    for (int cls = 0; cls < 2; ++cls) {
-                        st = timed_launch(c, kind, [&](const LaunchTiming &t) {
-                            return launch_cl_row_or(p, cls, cnt, c->stream, t);
-                        });
-                        if (st != PT_OK) return st;
-                    }
-                    if (n == total - 1) {
-                        const ClParams q = cl_params(c, k, first, 1, hb);
-                        st = timed_launch(c, kEnergyOnly, [&](const LaunchTiming &t) {
-                            return launch_cl_half_sweep(kEnergyOnly, true, q, cnt, c->stream, t);
-                        });
-                        if (st != PT_OK) return st;
-                    }
-                    continue;
-                }
-                for (int colour = 0; colour < 2; ++colour) {
-                    const bool energy = n == total - 1 && colour == 1;
-                    const ClParams p = cl_params(c, k, first, colour, hb);
-                    st = timed_launch(c, kind, [&](const LaunchTiming &t) {
-                        return launch_cl_half_sweep(kind, energy, p, cnt, c->stream, t);
+                if (n == total - 1) {
+                    const ClParams q = cl_params(c, k, first, 1, hb);
+                    st = timed_launch(c, kEnergyOnly, [&](const LaunchTiming &t) {
+                        return launch_cl_half_sweep(kEnergyOnly, true, q, cnt, c->stream, t);
                     });
                     if (st != PT_OK) return st;
                 }
-                if (kind == kHeatbath) ++hb;
+                continue;
             }
+            for (int colour = 0; colour < 2; ++colour) {
+                const bool energy = n == total - 1 && colour == 1;
+                const ClParams p = cl_params(c, k, first, colour, hb);
+                st = timed_launch(c, kind, [&](const LaunchTiming &t) {
+                    return launch_cl_half_sweep(kind, energy, p, cnt, c->stream, t);
+                });
+                if (st != PT_OK) return st;
+            }
+            if (kind == kHeatbath) ++hb;
         }
     }
     return finalize_energies(c, k);
@@ -817,7 +906,8 @@ static pt_status autotuned_tiles(const pt_batch_desc *d, std::vector<Tile> &tile
 // The autotuner runs only when no mapping is forced by a flag.
 static bool wants_autotune(const pt_batch_desc *d)
 {
-    const unsigned forced = PT_F_SITE_LANES | PT_F_CHAIN_LANES | PT_F_RESIDENT | PT_F_PLAIN | PT_F_ROW_OR;
+    const unsigned forced = PT_F_SITE_LANES | PT_F_CHAIN_LANES | PT_F_RESIDENT | PT_F_PLAIN | PT_F_ROW_OR |
+                            PT_F_PERSISTENT;
     return (d->flags & PT_F_AUTOTUNE) && !(d->flags & forced);
 }
 
@@ -913,6 +1003,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     c->bm_D = reinterpret_cast<float *>(w + P.off_bmD);
     c->use_graphs = (d->flags & PT_F_GRAPHS) != 0;
     c->row_or = (d->flags & PT_F_ROW_OR) != 0;
+    c->persistent = (d->flags & PT_F_PERSISTENT) != 0;
     {
         const uint32_t zero[2] = {0u, 0u};
         PT_HIP(hipMemcpy(c->counters, zero, sizeof(zero), hipMemcpyHostToDevice));
@@ -1288,6 +1379,94 @@ static pt_status queue_step(pt_ctx *c, int n_hb, int n_or)
     return PT_OK;
 }
 
+// PT_F_PERSISTENT: the step's descriptors, class by class, merged into
+// phases: phase i holds the i-th descriptor of every class whose sequence
+// is that long (classes share no data, and a descriptor depends at most on
+// those before it in its own class).  The grid is what the device keeps
+// resident, rounded down to whole XCD rounds (a multiple of 8, so that
+// workgroup w and every virtual block it takes sit on the same XCD), and
+// no larger than the widest phase.
+static pt_status build_program(pt_ctx *c, int n_hb, int n_or, pt_ctx::Program &g)
+{
+    std::vector<std::vector<StepDesc>> seqs;
+    size_t longest = 0;
+    for (const auto &k : c->classes) {
+        std::vector<int> kinds(n_hb, kHeatbath);
+        kinds.insert(kinds.end(), n_or == PT_OR_L ? k.L : n_or, kOverrelax);
+        seqs.push_back(class_sequence(c, k, kinds));
+        longest = std::max(longest, seqs.back().size());
+    }
+    int64_t widest = 0;
+    for (size_t ph = 0; ph < longest; ++ph) {
+        g.first.push_back(static_cast<int>(g.desc.size()));
+        int64_t blocks = 0;
+        for (const auto &q : seqs)
+            if (ph < q.size()) {
+                g.desc.push_back(q[ph]);
+                blocks += q[ph].n_blocks;
+            }
+        if (blocks > (int64_t(1) << 30)) return fail(PT_EINVAL, "persistent step: a phase has too many workgroups");
+        g.blocks.push_back(static_cast<int>(blocks));
+        widest = std::max(widest, blocks);
+    }
+    const bool chain = c->classes[0].lanes != 1;   // one mapping serves the batch
+    int cus = 0;
+    PT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    const int per_cu = chain ? cl_step_blocks_per_cu() : site_step_blocks_per_cu();
+    const int cap = per_cu * cus / kXcds * kXcds;
+    if (cap < kXcds) return fail(PT_EDEVICE, "persistent step: the kernel does not fit the device");
+    g.grid = static_cast<int>(std::min<int64_t>(cap, (widest + kXcds - 1) / kXcds * kXcds));
+    const size_t b_desc = align_up(sizeof(StepDesc) * g.desc.size());
+    const size_t b_int = align_up(sizeof(int) * g.first.size());
+    void *mem = nullptr;
+    if (hipMalloc(&mem, b_desc + 2 * b_int) != hipSuccess)
+        return fail(PT_ENOMEM, "hipMalloc of the persistent step program failed");
+    g.mem = static_cast<char *>(mem);
+    g.d_desc = reinterpret_cast<const StepDesc *>(g.mem);
+    g.d_first = reinterpret_cast<const int *>(g.mem + b_desc);
+    g.d_blocks = reinterpret_cast<const int *>(g.mem + b_desc + b_int);
+    PT_HIP(hipMemcpy(g.mem, g.desc.data(), sizeof(StepDesc) * g.desc.size(), hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(g.mem + b_desc, g.first.data(), sizeof(int) * g.first.size(), hipMemcpyHostToDevice));
+    PT_HIP(hipMemcpy(g.mem + b_desc + b_int, g.blocks.data(), sizeof(int) * g.blocks.size(),
+                     hipMemcpyHostToDevice));
+    return PT_OK;
+}
+
+// One persistent launch for the step (the heat-bath counter advances inside).
+static pt_status persistent_step(pt_ctx *c, int n_hb, int n_or)
+{
+    pt_status st;
+    auto it = c->programs.find({n_hb, n_or});
+    if (it == c->programs.end()) {
+        pt_ctx::Program g;
+        if ((st = build_program(c, n_hb, n_or, g)) != PT_OK) {
+            if (g.mem) (void)hipFree(g.mem);
+            return st;
+        }
+        it = c->programs.emplace(std::make_pair(n_hb, n_or), std::move(g)).first;
+    }
+    const pt_ctx::Program &g = it->second;
+    PersistParams p{};
+    p.desc = g.d_desc;
+    p.phase_first = g.d_first;
+    p.phase_blocks = g.d_blocks;
+    p.n_phases = static_cast<int>(g.first.size());
+    p.counters = c->counters;
+    p.d_hb = static_cast<uint32_t>(n_hb);
+    Event ev;
+    if (c->profiling) {
+        if (c->pending.size() >= 4096 && (st = drain_events(c)) != PT_OK) return st;
+        if ((st = get_event(c, ev)) != PT_OK) return st;
+        PT_HIP(hipEventRecord(ev.a, c->stream));
+    }
+    PT_HIP(c->classes[0].lanes != 1 ? launch_cl_step(p, g.grid, c->stream) : launch_site_step(p, g.grid, c->stream));
+    if (c->profiling) {
+        PT_HIP(hipEventRecord(ev.b, c->stream));
+        c->pending.push_back({PT_K_PERSISTENT, ev});
+    }
+    return PT_OK;
+}
+
 pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
 {
     pt_status st = check_ctx(c);
@@ -1295,7 +1474,9 @@ pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
     if (n_hb < 0 || (n_or < 0 && n_or != PT_OR_L))
         return fail(PT_EINVAL, "n_hb must be >= 0 and n_or >= 0 or PT_OR_L");
     if (n_hb == 0 && n_or == 0) return PT_OK;
-    if (!c->use_graphs || c->profiling) {
+    if (c->persistent) {
+        if ((st = persistent_step(c, n_hb, n_or)) != PT_OK) return st;
+    } else if (!c->use_graphs || c->profiling) {
         if ((st = queue_step(c, n_hb, n_or)) != PT_OK) return st;
     } else {
         // A step's launch sequence depends only on (n_hb, n_or): capture it
@@ -1805,7 +1986,7 @@ pt_status pt_profile(pt_ctx *c, int enable)
     if (st != PT_OK) return st;
     if ((st = drain_events(c)) != PT_OK) return st;
     c->profiling = enable != 0;
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < 4; ++q) {
         c->prof_launches[q] = 0;
         c->prof_ms[q] = 0.0;
     }
@@ -1816,7 +1997,7 @@ pt_status pt_kernel_time(pt_ctx *c, int kind, uint64_t *launches, double *ms)
 {
     pt_status st = check_ctx(c);
     if (st != PT_OK) return st;
-    if (kind != PT_K_OVERRELAX && kind != PT_K_HEATBATH && kind != PT_K_RESIDENT)
+    if (kind != PT_K_OVERRELAX && kind != PT_K_HEATBATH && kind != PT_K_RESIDENT && kind != PT_K_PERSISTENT)
         return fail(PT_EINVAL, "unknown kernel kind");
     if ((st = drain_events(c)) != PT_OK) return st;
     if (launches) *launches = c->prof_launches[kind];
@@ -1835,6 +2016,7 @@ void pt_free(pt_ctx *c)
         (void)hipEventDestroy(e.b);
     }
     for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &g : c->programs) (void)hipFree(g.second.mem);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);
     delete c;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kernels.hpp"
+
 namespace ptsg {
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -78,6 +80,25 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// E[chain] = -(sum of its partials) for chain bx*4 + (wave) of sample
+// samples[by]: lane l adds the partials l, l+64, ... in order, then the lanes
+// are combined by the fixed shuffle tree of wave_sum (a fixed order:
+// bit-reproducible).  Waves past the last chain return at once.
+template <class Params>
+__device__ __forceinline__ void energy_finalize_block(Params &P, unsigned bx, unsigned by)
+{
+    const int s = P.samples[by];
+    const int j = static_cast<int>(bx * 4 + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (j >= P.C) return;   // wave-uniform
+    const int chain = P.chain_base[s] + j;
+    const double *e = P.e_part + static_cast<int64_t>(chain) * P.e_stride;
+    double acc = 0.0;
+    for (int b = lane; b < P.n_blocks; b += 64) acc += e[b];
+    acc = wave_sum(acc);
+    if (lane == 0) P.E[chain] = -acc;
+}
+
 // Buffer-resource access: the chain's base address and size live in
 // SGPRs, each lane supplies a 32-bit byte offset, and the component stride
 // goes in the scalar offset, so addressing costs no vector ALU work.
@@ -105,8 +126,8 @@ __device__ __forceinline__ void st(Rsrc r, float v, unsigned voff, unsigned soff
 // with its own L2: workgroup w runs on XCD w % 8.  Tile t = xcd_tile(w, per)
 // gives XCD x the contiguous tiles [x*per, (x+1)*per), so that spatially
 // neighbouring tiles (whose spins a half-sweep reads as halo) share an L2.
-// The grid has 8*per workgroups; those mapped beyond the last tile exit.
-constexpr int kXcds = 8;
+// The grid has 8*per (kXcds*per) workgroups; those mapped beyond the last
+// tile exit.
 
 __device__ __forceinline__ int xcd_tile(int w, int per) { return (w % kXcds) * per + w / kXcds; }
 

@@ -9,6 +9,8 @@
 // coalesced component rows.  Same-colour sites share no bond (appendix A.1),
 // so all lanes update independently and the result does not depend on the
 // schedule.
+#include <hip/hip_cooperative_groups.h>
+
 #include "kernels.hpp"
 #include "philox.hpp"
 #include "spin_update.hpp"
@@ -126,12 +128,17 @@ __device__ __forceinline__ void decode_bonds(uint32_t lo, uint32_t hi, float D, 
     }
 }
 
-template <int KIND, bool ENERGY, bool BM>
-__global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
+using EWave = double[kSweepBlock / 64][kMaxGroup];
+
+// One workgroup's share of a half-sweep: block (bx, by, bz) of the launch
+// grid (8*per, ceil(C/G), samples).  `e_wave` is LDS for the energy
+// partials (ENERGY only).
+template <int KIND, bool ENERGY, bool BM, class Params>
+__device__ __forceinline__ void half_sweep_block(Params &P, unsigned bx, unsigned by, unsigned bz, EWave *e_wave)
 {
     constexpr bool kOwn = KIND != kHeatbath;  // heat-bath ignores the old spin
-    const int s = P.samples[blockIdx.z];
-    const int tile = xcd_tile(blockIdx.x, P.per);
+    const int s = P.samples[bz];
+    const int tile = xcd_tile(bx, P.per);
     if (tile >= P.n_tiles) return;
     const int p = tile * kSweepBlock + threadIdx.x;
     const bool active = p < P.H;
@@ -158,13 +165,12 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
         for (int m = 0; m < 54; ++m) A[m] = ld(rc, o, static_cast<unsigned>(m) * H4);
     }
 
-    const int j0 = blockIdx.y * P.G;
+    const int j0 = by * P.G;
     const int j1 = min(j0 + P.G, P.C);
     const int cb = P.chain_base[s];
     const int64_t stride = 6 * static_cast<int64_t>(H);
     const float *chain0 = P.spins + P.spin_base[s] + static_cast<int64_t>(j0) * stride;
     const unsigned chain_bytes = 6u * H4;
-    __shared__ double e_wave[kSweepBlock / 64][kMaxGroup];
 
     auto rsrc_of = [&](int j) { return make_rsrc(chain0 + static_cast<int64_t>(j - j0) * stride, chain_bytes); };
 
@@ -183,7 +189,7 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
         if constexpr (ENERGY) {
             // every bond has exactly one end of colour 1: E = -sum_{colour 1} s.h
             const double w = wave_sum(active ? e : 0.0);
-            if ((threadIdx.x & 63) == 0) e_wave[threadIdx.x >> 6][j - j0] = w;
+            if ((threadIdx.x & 63) == 0) (*e_wave)[threadIdx.x >> 6][j - j0] = w;
         }
     };
 
@@ -206,27 +212,79 @@ __global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
         for (int t = threadIdx.x; t < nj; t += kSweepBlock) {
             double e = 0.0;
 #pragma unroll
-            for (int w = 0; w < kSweepBlock / 64; ++w) e += e_wave[w][t];
+            for (int w = 0; w < kSweepBlock / 64; ++w) e += (*e_wave)[w][t];
             P.e_part[static_cast<int64_t>(cb + j0 + t) * P.e_stride + tile] = e;
         }
     }
 }
 
-// E[chain] = -(sum of its partials): one wave per chain, lane l adds the
-// partials l, l+64, ... in order, then the lanes are combined by the fixed
-// shuffle tree of wave_sum (a fixed order: bit-reproducible).
+template <int KIND, bool ENERGY, bool BM>
+__global__ __launch_bounds__(kSweepBlock) void half_sweep_kernel(SweepParams P)
+{
+    if constexpr (ENERGY) {
+        __shared__ EWave e_wave;
+        half_sweep_block<KIND, ENERGY, BM>(P, blockIdx.x, blockIdx.y, blockIdx.z, &e_wave);
+    } else {
+        half_sweep_block<KIND, ENERGY, BM>(P, blockIdx.x, blockIdx.y, blockIdx.z, nullptr);
+    }
+}
+
+// The persistent step in this mapping: the phases of a step's descriptors
+// (site-lane half-sweeps and energy finalisations), a grid-wide barrier
+// after each; the descriptors and phase tables are read-only for the
+// launch, so they are read through the constant address space (scalar
+// loads).
+using CDesc = __attribute__((address_space(4))) const StepDesc;
+using CInt = __attribute__((address_space(4))) const int;
+
+template <bool BM, class Params>
+__device__ __forceinline__ void site_dispatch(Params &p, int kind, int energy, unsigned bx, unsigned by,
+                                              unsigned bz, EWave *ew)
+{
+    if (kind == kOverrelax) {
+        if (energy) half_sweep_block<kOverrelax, true, BM>(p, bx, by, bz, ew);
+        else half_sweep_block<kOverrelax, false, BM>(p, bx, by, bz, ew);
+    } else if (kind == kHeatbath) {
+        if (energy) half_sweep_block<kHeatbath, true, BM>(p, bx, by, bz, ew);
+        else half_sweep_block<kHeatbath, false, BM>(p, bx, by, bz, ew);
+    } else {
+        half_sweep_block<kEnergyOnly, true, BM>(p, bx, by, bz, ew);
+    }
+}
+
+__global__ __launch_bounds__(kSweepBlock) void site_step_kernel(PersistParams P)
+{
+    __shared__ EWave e_wave;
+    const CDesc *desc = (const CDesc *)(P.desc);
+    const CInt *first = (const CInt *)(P.phase_first);
+    const CInt *blocks = (const CInt *)(P.phase_blocks);
+    for (int ph = 0; ph < P.n_phases; ++ph) {
+        const unsigned n = static_cast<unsigned>(blocks[ph]);
+        for (unsigned v = blockIdx.x; v < n; v += gridDim.x) {
+            int d = first[ph];
+            unsigned off = v;
+            while (off >= static_cast<unsigned>(desc[d].n_blocks)) off -= desc[d].n_blocks, ++d;
+            const unsigned gx = desc[d].gx, gy = desc[d].gy;
+            const unsigned bx = off % gx, r = off / gx, by = r % gy, bz = r / gy;
+            if (desc[d].op == kOpFinalize) {
+                energy_finalize_block(desc[d].ep, bx, by);
+            } else {
+                auto &p = desc[d].sp;
+                const int kind = desc[d].kind, energy = desc[d].energy;
+                if (p.bimodal) site_dispatch<true>(p, kind, energy, bx, by, bz, &e_wave);
+                else site_dispatch<false>(p, kind, energy, bx, by, bz, &e_wave);
+            }
+            __syncthreads();   // e_wave is reused by the next block
+        }
+        cooperative_groups::this_grid().sync();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.d_hb) P.counters[0] += P.d_hb;
+}
+
+// One wave per chain (energy_finalize_block).
 __global__ __launch_bounds__(256) void energy_finalize_kernel(EnergyParams P)
 {
-    const int s = P.samples[blockIdx.y];
-    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (j >= P.C) return;   // wave-uniform
-    const int chain = P.chain_base[s] + j;
-    const double *e = P.e_part + static_cast<int64_t>(chain) * P.e_stride;
-    double acc = 0.0;
-    for (int b = lane; b < P.n_blocks; b += 64) acc += e[b];
-    acc = wave_sum(acc);
-    if (lane == 0) P.E[chain] = -acc;
+    energy_finalize_block(P, blockIdx.x, blockIdx.y);
 }
 
 // Hot start: z = 1 - 2u1 uniform on [-1,1], azimuth 2 pi u2 (uniform law on
@@ -314,6 +372,20 @@ hipError_t launch_half_sweep(int kind, bool energy, const SweepParams &p, int n_
     if (kind == kHeatbath)
         return energy ? go(half_sweep_kernel<kHeatbath, true, false>) : go(half_sweep_kernel<kHeatbath, false, false>);
     return go(half_sweep_kernel<kEnergyOnly, true, false>);
+}
+
+int site_step_blocks_per_cu()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, site_step_kernel, kSweepBlock, 0) != hipSuccess) return 0;
+    return n;
+}
+
+hipError_t launch_site_step(const PersistParams &p, int grid, hipStream_t st)
+{
+    void *args[] = {const_cast<PersistParams *>(&p)};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(site_step_kernel), dim3(grid),
+                                      dim3(kSweepBlock), args, 0, st);
 }
 
 hipError_t launch_energy_finalize(const EnergyParams &p, int n_samples, hipStream_t st)

@@ -25,6 +25,8 @@
 // the cache.  (Reading each bond once from the 108-byte canonical blocks
 // would make a sweep fit, but the four scattered scalar loads per site
 // measured slower than the one contiguous 216-byte block.)
+#include <hip/hip_cooperative_groups.h>
+
 #include "kernels.hpp"
 #include "philox.hpp"
 #include "spin_update.hpp"
@@ -72,12 +74,16 @@ __device__ __forceinline__ void cl_gather(ClGather &g, Rsrc r, unsigned voff, co
     if constexpr (OWN) load_site(g.o, r, voff, t.own);
 }
 
-template <int KIND, bool ENERGY>
-__global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
+using ClEWave = double[kClWaves][64];
+
+// One workgroup's share of a half-sweep: block (bx, bz) of the launch grid
+// (8*per, 1, items).  `e_wave` is LDS for the energy partials (ENERGY only).
+template <int KIND, bool ENERGY, class Params>
+__device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsigned bz, ClEWave *e_wave)
 {
     constexpr bool kOwn = KIND != kHeatbath;
-    const int s = P.items[2 * blockIdx.z];
-    const int g = P.items[2 * blockIdx.z + 1];
+    const int s = P.items[2 * bz];
+    const int g = P.items[2 * bz + 1];
     const int lane = threadIdx.x & 63;
     // wave-uniform (the compiler cannot infer it from threadIdx.x)
     const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
@@ -103,7 +109,7 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
     }
 
     // This wave's segment: packed row `row` (= y + L*z), x-halves [x0, x0 + len).
-    const int tile = xcd_tile(blockIdx.x, P.per);
+    const int tile = xcd_tile(bx, P.per);
     if (tile >= P.n_tiles) return;
     const int seg = tile * kClWaves + wave;
     const int rl = seg / P.split;                 // row in visiting order
@@ -210,19 +216,83 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
 
     if constexpr (ENERGY) {
         // the four waves hold the same 64 chains: reduce them in a fixed order
-        __shared__ double e_wave[kClWaves][64];
-        e_wave[wave][lane] = e_acc;
+        (*e_wave)[wave][lane] = e_acc;
         __syncthreads();
         if (wave == 0 && lane_on) {
             double e = 0.0;
 #pragma unroll
-            for (int w = 0; w < kClWaves; ++w) e += e_wave[w][lane];
+            for (int w = 0; w < kClWaves; ++w) e += (*e_wave)[w][lane];
             P.e_part[static_cast<int64_t>(P.chain_base[s] + j) * P.e_stride + tile] = e;
         }
     }
 }
 
+template <int KIND, bool ENERGY>
+__global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
+{
+    if constexpr (ENERGY) {
+        __shared__ ClEWave e_wave;
+        cl_half_sweep_block<KIND, ENERGY>(P, blockIdx.x, blockIdx.z, &e_wave);
+    } else {
+        cl_half_sweep_block<KIND, ENERGY>(P, blockIdx.x, blockIdx.z, nullptr);
+    }
+}
+
+// The persistent step in this mapping (see site_step_kernel).
+using CDesc = __attribute__((address_space(4))) const StepDesc;
+using CInt = __attribute__((address_space(4))) const int;
+
+__global__ __launch_bounds__(kClBlock) __attribute__((amdgpu_waves_per_eu(6))) void cl_step_kernel(PersistParams P)
+{
+    __shared__ ClEWave e_wave;
+    const CDesc *desc = (const CDesc *)(P.desc);
+    const CInt *first = (const CInt *)(P.phase_first);
+    const CInt *blocks = (const CInt *)(P.phase_blocks);
+    for (int ph = 0; ph < P.n_phases; ++ph) {
+        const unsigned n = static_cast<unsigned>(blocks[ph]);
+        for (unsigned v = blockIdx.x; v < n; v += gridDim.x) {
+            int d = first[ph];
+            unsigned off = v;
+            while (off >= static_cast<unsigned>(desc[d].n_blocks)) off -= desc[d].n_blocks, ++d;
+            const unsigned gx = desc[d].gx, gy = desc[d].gy;
+            const unsigned bx = off % gx, r = off / gx, by = r % gy, bz = r / gy;
+            if (desc[d].op == kOpFinalize) {
+                energy_finalize_block(desc[d].ep, bx, by);
+            } else {
+                auto &p = desc[d].cp;
+                const int kind = desc[d].kind, energy = desc[d].energy;
+                if (kind == kOverrelax) {
+                    if (energy) cl_half_sweep_block<kOverrelax, true>(p, bx, bz, &e_wave);
+                    else cl_half_sweep_block<kOverrelax, false>(p, bx, bz, &e_wave);
+                } else if (kind == kHeatbath) {
+                    if (energy) cl_half_sweep_block<kHeatbath, true>(p, bx, bz, &e_wave);
+                    else cl_half_sweep_block<kHeatbath, false>(p, bx, bz, &e_wave);
+                } else {
+                    cl_half_sweep_block<kEnergyOnly, true>(p, bx, bz, &e_wave);
+                }
+            }
+            __syncthreads();   // e_wave is reused by the next block
+        }
+        cooperative_groups::this_grid().sync();
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && P.d_hb) P.counters[0] += P.d_hb;
+}
+
 }  // namespace
+
+int cl_step_blocks_per_cu()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cl_step_kernel, kClBlock, 0) != hipSuccess) return 0;
+    return n;
+}
+
+hipError_t launch_cl_step(const PersistParams &p, int grid, hipStream_t st)
+{
+    void *args[] = {const_cast<PersistParams *>(&p)};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(cl_step_kernel), dim3(grid),
+                                      dim3(kClBlock), args, 0, st);
+}
 
 int cl_blocks(int L, int split) { return (L * L * split + kClWaves - 1) / kClWaves; }
 

@@ -15,10 +15,11 @@ LIB_PATH = os.path.join(_PKG, "libptsg.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PT_M_OVERLAP, PT_M_CHIRAL, PT_M_SD, PT_M_ALL = 1, 2, 4, 7
-PT_K_OVERRELAX, PT_K_HEATBATH, PT_K_RESIDENT = 0, 1, 2
+PT_K_OVERRELAX, PT_K_HEATBATH, PT_K_RESIDENT, PT_K_PERSISTENT = 0, 1, 2, 3
 PT_F_SITE_LANES, PT_F_CHAIN_LANES, PT_F_RESIDENT, PT_F_GRAPHS, PT_F_PLAIN, PT_F_AUTOTUNE, PT_F_BIMODAL = \
     1, 2, 4, 8, 16, 32, 64
 PT_F_ROW_OR = 128
+PT_F_PERSISTENT = 256
 PT_OR_L = -1   # pt_step: L overrelaxation sweeps for a sample of linear size L
 
 # numpy view of the C struct pt_meas (744 bytes, no padding)

@@ -65,3 +65,31 @@ def assert_spins_close(gpu, ref, hmag, what=""):
            f"{bad.size} beyond the |h|-scaled bound")
     assert bad.size == 0, msg + f"; first at site {bad[0]} (|h| = {hmag[bad[0]]:.3g}, |ds| = {d[bad[0]]:.3g})"
     return d.max(), int(np.count_nonzero(d > TOL))
+
+
+def assert_resynced_sweep(L, M, before, after, kind, beta, seed, hb_sweep, sample, tslot, rep, sites=None,
+                          what=""):
+    """One GPU sweep checked site by site on the oracle, re-synced: a
+    colour-0 site is updated from the state before the sweep, a colour-1
+    site from that state with colour 0 replaced by the GPU's own colour-0
+    result (what the GPU's second half-sweep saw), so FP32 differences of
+    the first half-sweep do not propagate into the second.  Each site must
+    meet |ds| <= TOL * max(1, H_C/|h|).  Returns the largest |ds|."""
+    col = colours(L)
+    pre = np.asarray(before, np.float64)
+    mixed = np.where(col[:, None] == 0, np.asarray(after, np.float64), pre)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    worst = 0.0
+    for i in (range(L ** 3) if sites is None else sites):
+        state = pre if col[i] == 0 else mixed
+        h = O.local_field(L, M, state, int(i))
+        if kind == 0:
+            ref = O.overrelax_spin(h, state[i])
+        else:
+            w = O.philox(key, [int(i), hb_sweep, sample, O.ctr3(O.TAG_HB, tslot, rep)])
+            ref = O.heatbath_spin(h, beta, O.u23(w[0]), O.u23(w[1]))
+        d = float(np.linalg.norm(after[i] - ref))
+        hn = float(np.linalg.norm(h))
+        assert d <= TOL * max(1.0, H_C / hn), f"{what}: site {int(i)}: |ds| = {d:.3g} at |h| = {hn:.3g}"
+        worst = max(worst, d)
+    return worst
