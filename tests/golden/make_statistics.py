@@ -23,12 +23,17 @@ Configurations (the parity workloads of the hot path):
   L8:  L = 8, 8 temperatures evenly spaced in [0.5, 2.0], 2 replicas,
        1000 steps of 1 HB + 8 OR + PT; 64 runs.
   L16: L = 16, 16 geometric temperatures in [0.5, 2.0], 2 replicas,
-       10^4 steps of 1 HB + 16 OR + PT; 16 runs.
+       10^4 steps of 1 HB + 16 OR + PT; 32 runs.
 Couplings: the presets' (inputs.preset_inputs), one sample shared by all
 runs.  Run i draws its random numbers as sample i of seed ORACLE_SEED (the
 GPU side uses the presets' seed: independent streams).
 
-Usage: python tests/golden/make_statistics.py L8 [L16] [--procs 8]
+The GPU side of the test runs `gpu_runs` runs (GPU runs cost little, so
+more of them shrink the GPU share of the error).
+
+Usage: python tests/golden/make_statistics.py L8 [L16] [--procs 8] [--extend]
+(--extend keeps the runs already in the file and adds the missing ones:
+run i depends only on i.)
 """
 import argparse
 import json
@@ -45,8 +50,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 CONFIGS = {
-    "L8": dict(preset="L8", L=8, steps=1000, runs=64),
-    "L16": dict(preset="L16", L=16, steps=10000, runs=16),
+    "L8": dict(preset="L8", L=8, steps=1000, runs=64, gpu_runs=64),
+    "L16": dict(preset="L16", L=16, steps=10000, runs=32, gpu_runs=64),
 }
 ORACLE_SEED = 7130915990
 OBSERVABLES = ("e", "q2", "q4", "qk2")
@@ -104,18 +109,25 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("configs", nargs="+", choices=list(CONFIGS))
     ap.add_argument("--procs", type=int, default=os.cpu_count() or 1)
+    ap.add_argument("--extend", action="store_true")
     a = ap.parse_args()
     for name in a.configs:
         c = CONFIGS[name]
+        path = os.path.join(HERE, f"statistics_{name}.json")
+        runs = []
+        if a.extend and os.path.exists(path):
+            with open(path) as f:
+                old = json.load(f)
+            if old["steps"] == c["steps"] and old["oracle_seed"] == ORACLE_SEED:
+                runs = old["runs"][:c["runs"]]
         t0 = time.time()
         with mp.get_context("spawn").Pool(a.procs) as pool:
-            runs = pool.map(_one_run, [(name, i) for i in range(c["runs"])], chunksize=1)
+            runs += pool.map(_one_run, [(name, i) for i in range(len(runs), c["runs"])], chunksize=1)
         out = dict(config=name, preset=c["preset"], L=c["L"], steps=c["steps"], n_runs=c["runs"],
                    oracle_seed=ORACLE_SEED, observables=list(OBSERVABLES),
                    note="second-half means per run and slot; written by tests/golden/make_statistics.py "
                         "from the FP64 oracle only",
                    runs=runs)
-        path = os.path.join(HERE, f"statistics_{name}.json")
         with open(path, "w") as f:
             json.dump(out, f, indent=0)
         print(f"{name}: {c['runs']} runs in {time.time() - t0:.0f} s -> {path}", flush=True)

@@ -7,16 +7,16 @@ App. A.1) from the same hot-start law, so any statistic of a run of fixed
 length has the same distribution on both sides, equilibrated or not.  The
 oracle side is stored (tests/golden/statistics_<config>.json, written by
 tests/golden/make_statistics.py from the oracle alone); the GPU side runs
-the same number of independent runs as the samples of one batch (one
-coupling realisation shared by all, each sample drawing its own random
-numbers).  Errors are the spread between runs, so metastable runs at the
+independent runs as the samples of one batch (one coupling realisation
+shared by all, each sample drawing its own random numbers); GPU runs cost
+little, so there are more of them than oracle runs.  Errors are the spread between runs, so metastable runs at the
 lowest temperature widen the error instead of biasing the comparison.
 
 Workloads:
   L8:  L = 8, 8 temperatures evenly spaced in [0.5, 2.0], 2 replicas,
        1000 steps, 64 runs per side;
   L16: L = 16, 16 geometric temperatures in [0.5, 2.0], 2 replicas,
-       10^4 steps, 16 runs per side.
+       10^4 steps, 32 oracle runs and 64 GPU runs.
 Observables per temperature, over the second half of each run (measurement
 after every tempering pass): energy per spin, <q^2>, <q^4> of q = tr Q(0),
 and xi/L from the second-moment formula of Sec. II.B (jackknife over runs).
@@ -52,7 +52,7 @@ def _gpu():
 def _gpu_runs(name):
     c = MS.CONFIGS[name]
     Ls, cpl, temps, R, seed = inputs.preset_inputs(c["preset"])
-    L, T, n = Ls[0], len(temps[0]), c["runs"]
+    L, T, n = Ls[0], len(temps[0]), c["gpu_runs"]
     ctx = ptsg.pt_init_batch([L] * n, [cpl[0]] * n, [temps[0]] * n, R, seed, flags=ptsg.PT_F_GRAPHS)
     meas, recs = [], None
     for step in range(c["steps"]):
