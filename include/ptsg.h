@@ -160,10 +160,12 @@ enum {
     /* The paper's coupling family (Sec. II.A): every bond is
      * M = J*1 + D_sym, J = +-1, the six entries D_ab (a <= b) of the
      * symmetric D equal to +-D, one D > 0 per sample (checked bit for bit;
-     * PT_EINVAL otherwise).  Site-lane samples then keep one byte per bond
-     * (8 bytes per site instead of 216) and decode it in the sweep kernel;
-     * results are bit-identical to passing the same matrices without the
-     * flag.  Chain-lane and resident samples keep their float layouts. */
+     * PT_EINVAL otherwise).  Site-lane and chain-lane samples then keep one
+     * byte per bond (8 bytes per site instead of 216): site lanes decode it
+     * in the sweep kernel, chain lanes read each code's matrix from a
+     * per-sample table of the 128 codes; results are bit-identical to
+     * passing the same matrices without the flag.  Resident samples and the
+     * row order (PT_F_ROW_OR) keep the float layouts. */
     PT_F_BIMODAL = 64u,
     /* Overrelaxation sweeps in the row order (Sec. III, appendix A.3) instead
      * of the checkerboard: rows of 8 spins along x, row (b, y, z) holding

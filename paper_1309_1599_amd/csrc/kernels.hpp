@@ -79,6 +79,7 @@ struct SweepParams {
 struct ClParams {
     float *spins;
     const float *cpl;            // per-site packed couplings [colour][H][54] per sample
+                                 // (bimodal: 8 code bytes per site, [colour][H][8])
     const int *items;            // [n_items][2]: (sample, chain group)
     const int64_t *spin_base;
     const int64_t *cpl_base;
@@ -88,6 +89,8 @@ struct ClParams {
     double *e_part;
     int e_stride;
     int L, H, C, T;
+    int bimodal;                 // cpl holds bond codes; bm_table their matrices
+    const float *bm_table;       // [sample][128][9]: the matrix of each code (bimodal samples)
     int split;                   // waves per packed row (divides L/2)
     int strip;                   // row order: strips of `strip` y-rows, z-major within a strip (0: y-major)
     int n_tiles, per;            // workgroups of rows per item; per XCD (grid = 8*per)

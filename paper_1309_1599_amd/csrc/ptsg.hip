@@ -65,14 +65,14 @@ struct LatticeClass {
 struct Plan {
     int S = 0, R = 0, n_chains = 0, Lmax = 0, n_records = 0, e_stride = 1, twid_len = 0;
     std::vector<int> L, T, lanes, mapping, chain_base, perm_base, beta_base, twid_base;
-    std::vector<char> codes;          // per sample: bond codes instead of packed floats (PT_F_BIMODAL, site lanes)
+    std::vector<char> codes;          // per sample: bond codes instead of packed floats (PT_F_BIMODAL, site and chain lanes)
     std::vector<int64_t> spin_base, cpls_base, cpl6_base;
     int64_t spin_floats = 0, cpls_floats = 0, cpl6_floats = 0;
     int total_perm = 0, n_items = 0;
     size_t off_spins = 0, off_cpls = 0, off_cpl6 = 0, off_slot = 0, off_beta_of = 0, off_E = 0,
            off_perm = 0, off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0,
            off_mpart = 0, off_meas = 0, off_classes = 0, off_items = 0, off_stage = 0, off_counters = 0,
-           off_bmD = 0,
+           off_bmD = 0, off_bmtab = 0,
            bytes = 0;
 };
 
@@ -311,7 +311,9 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<Tile> *forced = nullptr
         twid += 2 * L;
         spins += static_cast<int64_t>(C_alloc) * 3 * N;
         cpls += 27 * N;
-        const bool codes = (d->flags & PT_F_BIMODAL) && mapping == kSiteLanes;
+        // the row-order kernel and the resident kernel read floats
+        const bool codes = (d->flags & PT_F_BIMODAL) &&
+                           (mapping == kSiteLanes || (mapping == kChainLanes && !(d->flags & PT_F_ROW_OR)));
         p.codes.push_back(codes);
         cpl6 += codes ? 2 * N : 54 * N;   // 8 bytes per site, or 54 floats
         if (lanes == 1) {
@@ -363,6 +365,8 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<Tile> *forced = nullptr
     p.off_stage = take(sizeof(float) * stage);
     p.off_counters = take(2 * sizeof(uint32_t));
     p.off_bmD = take(sizeof(float) * p.S);
+    // bimodal: per sample the matrix of each of the 128 codes (chain lanes)
+    p.off_bmtab = take(sizeof(float) * ((d->flags & PT_F_BIMODAL) ? 128 * 9 * static_cast<size_t>(p.S) : 1));
     p.bytes = o;
     return p;
 }
@@ -418,6 +422,7 @@ struct pt_ctx {
     float *stage = nullptr;           // one chain in canonical [N][3] order
     uint32_t *counters = nullptr;     // device: heat-bath sweeps, PT passes
     float *bm_D = nullptr;            // device, per sample: D of the bimodal family (PT_F_BIMODAL)
+    float *bm_table = nullptr;        // device, per sample: [128][9] matrix of each bond code
     bool use_graphs = false;
     bool row_or = false;              // PT_F_ROW_OR: overrelaxation sweeps in the row order
     hipStream_t capture_stream = nullptr;
@@ -493,6 +498,8 @@ ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour,
     p.H = k.L * k.L * k.L / 2;
     p.C = k.C;
     p.T = k.T;
+    p.bimodal = c->plan.codes[k.samples[0]];
+    p.bm_table = c->bm_table;
     p.split = k.split;
     p.strip = k.strip;
     p.n_tiles = k.blocks;
@@ -795,7 +802,7 @@ uint64_t fnv1a(const void *data, size_t n)
     return h;
 }
 
-// Bond codes of a bimodal sample for the site-lane kernel: out[colour][H][8],
+// Bond codes of a bimodal sample for the site-lane and chain-lane kernels: out[colour][H][8],
 // byte n of a site = code of its matrix A_n (n = 0..5: forward and backward
 // bond along x, y, z; the family is symmetric, so A_{2mu+1} = M_{mu,x-e_mu}
 // has the code of that bond), bytes 6 and 7 zero.
@@ -1001,6 +1008,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     c->stage = reinterpret_cast<float *>(w + P.off_stage);
     c->counters = reinterpret_cast<uint32_t *>(w + P.off_counters);
     c->bm_D = reinterpret_cast<float *>(w + P.off_bmD);
+    c->bm_table = reinterpret_cast<float *>(w + P.off_bmtab);
     c->use_graphs = (d->flags & PT_F_GRAPHS) != 0;
     c->row_or = (d->flags & PT_F_ROW_OR) != 0;
     c->persistent = (d->flags & PT_F_PERSISTENT) != 0;
@@ -1096,6 +1104,10 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
                 pack_bond_codes(L, d->couplings[s], D, codes.data());
                 PT_HIP(hipMemcpy(c->cpl6 + P.cpl6_base[s], codes.data(), codes.size(), hipMemcpyHostToDevice));
                 PT_HIP(hipMemcpy(c->bm_D + s, &D, sizeof(float), hipMemcpyHostToDevice));
+                std::vector<float> table(128 * 9);
+                for (unsigned code = 0; code < 128; ++code) bimodal_matrix(code, D, &table[9 * code]);
+                PT_HIP(hipMemcpy(c->bm_table + static_cast<size_t>(s) * 128 * 9, table.data(),
+                                 table.size() * sizeof(float), hipMemcpyHostToDevice));
                 continue;
             }
             buf.assign(static_cast<size_t>(54 * N), 0.0f);

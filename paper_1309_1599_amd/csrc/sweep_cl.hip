@@ -52,10 +52,12 @@ __device__ __forceinline__ void load_site(float (&v)[3], Rsrc r, unsigned voff, 
 }
 
 // Byte offsets (scalar) of the 7 sites a lane reads for one update, and the
-// float offset of the site's block in the packed couplings.
+// float offset of the site's block in the packed couplings (or, with bond
+// codes, the site's eight code bytes, read one site ahead).
 struct ClSite {
     unsigned own, nb[6];
     unsigned cpl;        // first of the site's 54 coupling floats
+    uint32_t lo, hi;     // bond codes of A_0..A_3 and A_4, A_5 (bimodal samples)
     int site;            // canonical index
 };
 
@@ -65,6 +67,9 @@ typedef float v2f __attribute__((ext_vector_type(2)));
 using CV16 = __attribute__((address_space(4))) const v16f;
 using CV4 = __attribute__((address_space(4))) const v4f;
 using CV2 = __attribute__((address_space(4))) const v2f;
+typedef float v8f __attribute__((ext_vector_type(8)));
+using CV8 = __attribute__((address_space(4))) const v8f;
+using CU32 = __attribute__((address_space(4))) const uint32_t;
 
 template <bool OWN>
 __device__ __forceinline__ void cl_gather(ClGather &g, Rsrc r, unsigned voff, const ClSite &t)
@@ -78,7 +83,7 @@ using ClEWave = double[kClWaves][64];
 
 // One workgroup's share of a half-sweep: block (bx, bz) of the launch grid
 // (8*per, 1, items).  `e_wave` is LDS for the energy partials (ENERGY only).
-template <int KIND, bool ENERGY, class Params>
+template <int KIND, bool ENERGY, bool BM, class Params>
 __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsigned bz, ClEWave *e_wave)
 {
     constexpr bool kOwn = KIND != kHeatbath;
@@ -98,6 +103,11 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
     // The couplings are read-only for the whole launch: reading them through
     // the constant address space lets wave-uniform loads become scalar loads.
     const CFloat *M = (const CFloat *)(P.cpl + P.cpl_base[s]);
+    // bimodal samples: eight code bytes per site in place of the 54 floats,
+    // and the sample's 128 decoded matrices (9 floats each), a table small
+    // enough to stay in the scalar cache
+    const CU32 *codes = (const CU32 *)(P.cpl + P.cpl_base[s]);
+    const CFloat *table = BM ? (const CFloat *)(P.bm_table) + s * (128 * 9) : nullptr;
 
     uint32_t ctr3 = 0, hb_sweep = 0;
     float beta = 0.0f;
@@ -137,7 +147,7 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
         const unsigned b_x = (oth + rowp) * kRow;
         const unsigned b_yp = (oth + yp) * kRow, b_ym = (oth + ym) * kRow;
         const unsigned b_zp = (oth + zp) * kRow, b_zm = (oth + zm) * kRow;
-        const unsigned c_row = (static_cast<unsigned>(c) * H + rowp) * 54u;
+        const unsigned c_site = static_cast<unsigned>(c) * H + rowp;   // packed index of (0, y, z), colour c
 
         auto site_at = [&](int xh) {
             ClSite t;
@@ -153,7 +163,11 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
             t.nb[4] = b_zp + o;
             t.nb[5] = b_zm + o;
             t.site = rowc + x;
-            t.cpl = c_row + static_cast<unsigned>(xh) * 54u;
+            t.cpl = (c_site + static_cast<unsigned>(xh)) * 54u;
+            if constexpr (BM) {
+                t.lo = codes[2 * (c_site + static_cast<unsigned>(xh))];
+                t.hi = codes[2 * (c_site + static_cast<unsigned>(xh)) + 1];
+            }
             return t;
         };
 
@@ -161,18 +175,38 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
             // The site's 54 coefficients in five scalar loads.  The empty asm
             // needs all of them at once, so the loads are issued together and
             // waited for once, instead of one round trip per load.
-            const CFloat *A = M + t.cpl;
-            const v16f a0 = *(CV16 *)(A);
-            const v16f a1 = *(CV16 *)(A + 16);
-            const v16f a2 = *(CV16 *)(A + 32);
-            const v4f a3 = *(CV4 *)(A + 48);
-            const v2f a4 = *(CV2 *)(A + 52);
-            asm volatile("" ::"s"(a0), "s"(a1), "s"(a2), "s"(a3), "s"(a4));
             float h[3];
-            local_field(gt.n, [&](int n, int a, int b) {
-                const int q = n * 9 + a * 3 + b;
-                return q < 16 ? a0[q] : q < 32 ? a1[q - 16] : q < 48 ? a2[q - 32] : q < 52 ? a3[q - 48] : a4[q - 52];
-            }, h);
+            if constexpr (BM) {
+                // the six matrices from the table, twelve scalar loads issued
+                // together (the codes arrived with the previous site)
+                v8f m8[6];
+                float m1[6];
+#pragma unroll
+                for (int n = 0; n < 6; ++n) {
+                    const uint32_t code = (n < 4 ? t.lo >> (8 * n) : t.hi >> (8 * (n - 4))) & 0x7fu;
+                    const CFloat *q = table + 9u * code;
+                    m8[n] = *(CV8 *)(q);
+                    m1[n] = q[8];
+                }
+                asm volatile("" ::"s"(m8[0]), "s"(m8[1]), "s"(m8[2]), "s"(m8[3]), "s"(m8[4]), "s"(m8[5]),
+                             "s"(m1[0]), "s"(m1[1]), "s"(m1[2]), "s"(m1[3]), "s"(m1[4]), "s"(m1[5]));
+                local_field(gt.n, [&](int n, int a, int b) {
+                    const int q = a * 3 + b;
+                    return q < 8 ? m8[n][q] : m1[n];
+                }, h);
+            } else {
+                const CFloat *A = M + t.cpl;
+                const v16f a0 = *(CV16 *)(A);
+                const v16f a1 = *(CV16 *)(A + 16);
+                const v16f a2 = *(CV16 *)(A + 32);
+                const v4f a3 = *(CV4 *)(A + 48);
+                const v2f a4 = *(CV2 *)(A + 52);
+                asm volatile("" ::"s"(a0), "s"(a1), "s"(a2), "s"(a3), "s"(a4));
+                local_field(gt.n, [&](int n, int a, int b) {
+                    const int q = n * 9 + a * 3 + b;
+                    return q < 16 ? a0[q] : q < 32 ? a1[q - 16] : q < 48 ? a2[q - 32] : q < 52 ? a3[q - 48] : a4[q - 52];
+                }, h);
+            }
             float sx, sy, sz;
             if constexpr (KIND == kHeatbath) {
                 const uint4 w = philox10(make_uint4(static_cast<uint32_t>(t.site), hb_sweep,
@@ -227,20 +261,34 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
     }
 }
 
-template <int KIND, bool ENERGY>
+template <int KIND, bool ENERGY, bool BM>
 __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
 {
     if constexpr (ENERGY) {
         __shared__ ClEWave e_wave;
-        cl_half_sweep_block<KIND, ENERGY>(P, blockIdx.x, blockIdx.z, &e_wave);
+        cl_half_sweep_block<KIND, ENERGY, BM>(P, blockIdx.x, blockIdx.z, &e_wave);
     } else {
-        cl_half_sweep_block<KIND, ENERGY>(P, blockIdx.x, blockIdx.z, nullptr);
+        cl_half_sweep_block<KIND, ENERGY, BM>(P, blockIdx.x, blockIdx.z, nullptr);
     }
 }
 
 // The persistent step in this mapping (see site_step_kernel).
 using CDesc = __attribute__((address_space(4))) const StepDesc;
 using CInt = __attribute__((address_space(4))) const int;
+
+template <bool BM, class Params>
+__device__ __forceinline__ void cl_dispatch(Params &p, int kind, int energy, unsigned bx, unsigned bz, ClEWave *ew)
+{
+    if (kind == kOverrelax) {
+        if (energy) cl_half_sweep_block<kOverrelax, true, BM>(p, bx, bz, ew);
+        else cl_half_sweep_block<kOverrelax, false, BM>(p, bx, bz, ew);
+    } else if (kind == kHeatbath) {
+        if (energy) cl_half_sweep_block<kHeatbath, true, BM>(p, bx, bz, ew);
+        else cl_half_sweep_block<kHeatbath, false, BM>(p, bx, bz, ew);
+    } else {
+        cl_half_sweep_block<kEnergyOnly, true, BM>(p, bx, bz, ew);
+    }
+}
 
 __global__ __launch_bounds__(kClBlock) __attribute__((amdgpu_waves_per_eu(6))) void cl_step_kernel(PersistParams P)
 {
@@ -261,15 +309,8 @@ __global__ __launch_bounds__(kClBlock) __attribute__((amdgpu_waves_per_eu(6))) v
             } else {
                 auto &p = desc[d].cp;
                 const int kind = desc[d].kind, energy = desc[d].energy;
-                if (kind == kOverrelax) {
-                    if (energy) cl_half_sweep_block<kOverrelax, true>(p, bx, bz, &e_wave);
-                    else cl_half_sweep_block<kOverrelax, false>(p, bx, bz, &e_wave);
-                } else if (kind == kHeatbath) {
-                    if (energy) cl_half_sweep_block<kHeatbath, true>(p, bx, bz, &e_wave);
-                    else cl_half_sweep_block<kHeatbath, false>(p, bx, bz, &e_wave);
-                } else {
-                    cl_half_sweep_block<kEnergyOnly, true>(p, bx, bz, &e_wave);
-                }
+                if (p.bimodal) cl_dispatch<true>(p, kind, energy, bx, bz, &e_wave);
+                else cl_dispatch<false>(p, kind, energy, bx, bz, &e_wave);
             }
             __syncthreads();   // e_wave is reused by the next block
         }
@@ -301,16 +342,19 @@ hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_
 {
     const dim3 grid(kXcds * p.per, 1, n_items);
     const dim3 block(kClBlock);
-    if (kind == kOverrelax) {
-        if (energy) return launch_kernel(cl_half_sweep_kernel<kOverrelax, true>, grid, block, 0, st, t, p);
-        else return launch_kernel(cl_half_sweep_kernel<kOverrelax, false>, grid, block, 0, st, t, p);
-    } else if (kind == kHeatbath) {
-        if (energy) return launch_kernel(cl_half_sweep_kernel<kHeatbath, true>, grid, block, 0, st, t, p);
-        else return launch_kernel(cl_half_sweep_kernel<kHeatbath, false>, grid, block, 0, st, t, p);
-    } else {
-        return launch_kernel(cl_half_sweep_kernel<kEnergyOnly, true>, grid, block, 0, st, t, p);
+    auto go = [&](auto kernel) { return launch_kernel(kernel, grid, block, 0, st, t, p); };
+    if (p.bimodal) {
+        if (kind == kOverrelax)
+            return energy ? go(cl_half_sweep_kernel<kOverrelax, true, true>) : go(cl_half_sweep_kernel<kOverrelax, false, true>);
+        if (kind == kHeatbath)
+            return energy ? go(cl_half_sweep_kernel<kHeatbath, true, true>) : go(cl_half_sweep_kernel<kHeatbath, false, true>);
+        return go(cl_half_sweep_kernel<kEnergyOnly, true, true>);
     }
-    return hipGetLastError();
+    if (kind == kOverrelax)
+        return energy ? go(cl_half_sweep_kernel<kOverrelax, true, false>) : go(cl_half_sweep_kernel<kOverrelax, false, false>);
+    if (kind == kHeatbath)
+        return energy ? go(cl_half_sweep_kernel<kHeatbath, true, false>) : go(cl_half_sweep_kernel<kHeatbath, false, false>);
+    return go(cl_half_sweep_kernel<kEnergyOnly, true, false>);
 }
 
 }  // namespace ptsg

@@ -1,8 +1,10 @@
 """The paper's coupling family stored as one byte per bond (PT_F_BIMODAL):
-site-lane samples decode the codes in the sweep kernel; the result must be
+site-lane samples decode the codes in the sweep kernel, chain-lane samples
+read each code's matrix from a per-sample table; the result must be
 bit-identical to passing the same matrices as floats, for the batched and
-the plain form, at D = 0.5 and D = 1, and one sweep must match the oracle
-replayed on the same state (the oracle takes the materialised matrices)."""
+the plain form and both mappings, at D = 0.5 and D = 1, and one sweep must
+match the oracle replayed on the same state (the oracle takes the
+materialised matrices)."""
 import numpy as np
 import pytest
 
@@ -33,7 +35,8 @@ def _run(Ls, cpl, temps, R, seed, flags):
 
 
 @pytest.mark.parametrize("D", [0.5, 1.0])
-@pytest.mark.parametrize("form", [ptsg.PT_F_SITE_LANES, ptsg.PT_F_PLAIN, 0], ids=["site", "plain", "auto"])
+@pytest.mark.parametrize("form", [ptsg.PT_F_SITE_LANES, ptsg.PT_F_PLAIN, ptsg.PT_F_CHAIN_LANES, 0],
+                         ids=["site", "plain", "chain", "auto"])
 def test_bytes_bit_identical_to_floats(D, form):
     Ls, T, R, seed = [12, 8, 20], 5, 2, 515
     cpl = [inputs.bimodal_couplings(L, D, seed, s) for s, L in enumerate(Ls)]
@@ -49,12 +52,27 @@ def test_bytes_bit_identical_to_floats(D, form):
         np.testing.assert_array_equal(x, y)
 
 
+def test_bytes_chain_lanes_automatic():
+    """Full 64-lane waves at L = 24 take chain lanes on their own; two
+    samples with different D."""
+    Ls, T, R, seed = [24, 24], 32, 2, 717
+    cpl = [inputs.bimodal_couplings(24, D, seed, s) for s, D in enumerate((0.5, 1.0))]
+    temps = [inputs.geometric_temps(0.6, 1.6, T)] * 2
+    a = _run(Ls, cpl, temps, R, seed, 0)
+    b = _run(Ls, cpl, temps, R, seed, ptsg.PT_F_BIMODAL)
+    assert a[3] == b[3] == [ptsg.PT_F_CHAIN_LANES] * 2
+    for x, y in zip(a[0] + a[1] + list(a[2]), b[0] + b[1] + list(b[2])):
+        np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("mapping", [ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES], ids=["site", "chain"])
 @pytest.mark.parametrize("kind", [0, 1], ids=["overrelax", "heatbath"])
-def test_bytes_one_sweep_matches_oracle(kind):
+def test_bytes_one_sweep_matches_oracle(kind, mapping):
     L, T, R, seed = 8, 3, 2, 616
     M = inputs.bimodal_couplings(L, 0.5, seed)
     temps = inputs.linear_temps(0.7, 1.5, T)
-    ctx = ptsg.pt_init_batch([L], [M], [temps], R, seed, flags=ptsg.PT_F_SITE_LANES | ptsg.PT_F_BIMODAL)
+    ctx = ptsg.pt_init_batch([L], [M], [temps], R, seed, flags=mapping | ptsg.PT_F_BIMODAL)
+    assert ptsg.pt_get_mapping(ctx, 0) == mapping
     s0 = {(r, k): ptsg.pt_get_spins(ctx, 0, r, k) for r in range(R) for k in range(T)}
     ptsg.pt_step(ctx, 1 if kind else 0, 0 if kind else 1)
     M64 = M.astype(np.float64)

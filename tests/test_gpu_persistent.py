@@ -36,8 +36,9 @@ CASES = [
     ("site", [12, 12, 8], [5, 5, 3], 3, 0, 2),
     # an uneven batch under the paper's step (1 HB + L OR per sample)
     ("mixed", [8, 12, 16, 24], [4, 5, 6, 8], 2, 0, ptsg.PT_OR_L),
-    # one-byte bimodal couplings (site lanes)
+    # one-byte bimodal couplings (site lanes, and chain lanes)
     ("bimodal", [8, 12], [4, 4], 2, ptsg.PT_F_BIMODAL, 2),
+    ("chain-bimodal", [24], [32], 2, ptsg.PT_F_BIMODAL, 2),
 ]
 
 
