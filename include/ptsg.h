@@ -72,7 +72,10 @@ enum {
     PT_M_OVERLAP = 1u, /* overlap tensor Q^{ab}(k), Sec. II.B */
     PT_M_CHIRAL = 2u,  /* chiral-glass overlap q_CG^mu(k), Sec. II.B */
     PT_M_SD = 4u,      /* Schwinger-Dyson sums, appendix A.4 */
-    PT_M_ALL = 7u
+    PT_M_ENERGY = 8u,  /* energies E_a, E_b and beta (Eq. (1); every record carries them,
+                        * so this bit alone asks for nothing else and launches no
+                        * lattice reduction) */
+    PT_M_ALL = 15u
 };
 
 /* One measurement record: replicas a < b of one sample at one temperature

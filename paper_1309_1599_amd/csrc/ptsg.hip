@@ -1598,7 +1598,7 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
         };
         for (int s = 0; s < P.S; ++s) {
             const int n = P.T[s] * P.R * (P.R - 1) / 2;
-            if (P.lanes[s] != 1) {
+            if (P.lanes[s] != 1 && (what & (PT_M_OVERLAP | PT_M_CHIRAL | PT_M_SD))) {
                 PT_HIP(flush(first));
                 const int L = P.L[s];
                 PT_HIP(launch_cl_to_sl(c->spins, P.spin_base[s], L * L * L / 2, P.R * P.T[s], c->stage,

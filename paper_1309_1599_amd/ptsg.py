@@ -14,7 +14,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libptsg.so")
 
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_ESTATE, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PT_M_OVERLAP, PT_M_CHIRAL, PT_M_SD, PT_M_ALL = 1, 2, 4, 7
+PT_M_OVERLAP, PT_M_CHIRAL, PT_M_SD, PT_M_ENERGY, PT_M_ALL = 1, 2, 4, 8, 15
 PT_K_OVERRELAX, PT_K_HEATBATH, PT_K_RESIDENT, PT_K_PERSISTENT = 0, 1, 2, 3
 PT_F_SITE_LANES, PT_F_CHAIN_LANES, PT_F_RESIDENT, PT_F_GRAPHS, PT_F_PLAIN, PT_F_AUTOTUNE, PT_F_BIMODAL = \
     1, 2, 4, 8, 16, 32, 64

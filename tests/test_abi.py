@@ -131,17 +131,23 @@ def test_checkpoint_calls_need_a_context(lib):
 def test_bimodal_flag_validates_the_family(lib):
     """PT_F_BIMODAL accepts the paper's family bit for bit (D = 0.5 and D = 1,
     where diagonals can be exactly 0) and stores 8 bytes of codes per site
-    for site-lane samples instead of 54 floats; anything else is refused."""
+    for site-lane and chain-lane samples instead of 54 floats (plus the
+    sample's table of 128 code matrices); anything else is refused."""
     L, T, R = 8, 4, 2
     N = L ** 3
     temps = [inputs.geometric_temps(0.5, 1.5, T)]
-    f = ptsg.PT_F_SITE_LANES
-    for D in (0.5, 1.0):
-        cpl = [inputs.bimodal_couplings(L, D, 3)]
-        plain = ptsg.pt_workspace_size([L], cpl, temps, R, flags=f)
-        packed = ptsg.pt_workspace_size([L], cpl, temps, R, flags=f | ptsg.PT_F_BIMODAL)
-        assert packed > 0
-        assert plain - packed == pytest.approx(4 * (54 - 2) * N, abs=4096)
+    for f in (ptsg.PT_F_SITE_LANES, ptsg.PT_F_CHAIN_LANES):
+        for D in (0.5, 1.0):
+            cpl = [inputs.bimodal_couplings(L, D, 3)]
+            plain = ptsg.pt_workspace_size([L], cpl, temps, R, flags=f)
+            packed = ptsg.pt_workspace_size([L], cpl, temps, R, flags=f | ptsg.PT_F_BIMODAL)
+            assert packed > 0
+            assert plain - packed == pytest.approx(4 * (54 - 2) * N - 4 * 128 * 9, abs=1024)
+    # the resident kernel keeps the floats: only the table is added
+    cpl = [inputs.bimodal_couplings(L, 0.5, 3)]
+    plain = ptsg.pt_workspace_size([L], cpl, temps, R, flags=ptsg.PT_F_RESIDENT)
+    packed = ptsg.pt_workspace_size([L], cpl, temps, R, flags=ptsg.PT_F_RESIDENT | ptsg.PT_F_BIMODAL)
+    assert packed - plain == pytest.approx(4 * 128 * 9, abs=512)
 
     def refused(M):
         ok = ptsg.pt_workspace_size([L], [M], temps, R, flags=ptsg.PT_F_BIMODAL) > 0

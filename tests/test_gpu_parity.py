@@ -390,3 +390,29 @@ def test_step_with_L_overrelaxation_sweeps_per_sample(Ls):
         ptsg.pt_step(both, 1, -2)
     ptsg.pt_free(both)
     ptsg.pt_free(alone)
+
+
+def test_measure_energy_bit_alone():
+    """PT_M_ENERGY alone: every record carries beta and the energies of its
+    two chains, as pt_get_energy gives them after tempering has moved chains
+    between slots, and nothing else; a resident and a chain-lane sample."""
+    Ls, T, R, seed = [8, 24], 32, 2, 950
+    temps = [inputs.geometric_temps(0.6, 1.6, T)] * 2
+    ctx, _ = _ctx(Ls, temps, R, seed)
+    assert [ptsg.pt_get_mapping(ctx, s) for s in range(2)] == [ptsg.PT_F_RESIDENT, ptsg.PT_F_CHAIN_LANES]
+    for _ in range(3):
+        ptsg.pt_step(ctx, 1, 2)
+        ptsg.pt_swap(ctx)
+    recs = ptsg.pt_measure(ctx, ptsg.PT_M_ENERGY)
+    E = ptsg.pt_get_energy(ctx)
+    assert len(recs) == 2 * T
+    for rec in recs:
+        s, k, a, b = int(rec["sample"]), int(rec["tslot"]), int(rec["rep_a"]), int(rec["rep_b"])
+        assert rec["E_a"] == E[s][a, k] and rec["E_b"] == E[s][b, k]
+        assert rec["beta"] == 1.0 / temps[s][k]
+        for f in ("q0", "qk_re", "qk_im", "cg0", "cgk_re", "cgk_im", "sd1_a", "sd2_a", "sd1_b", "sd2_b"):
+            assert not np.any(rec[f]), f
+    full = ptsg.pt_measure(ctx, ptsg.PT_M_ALL)
+    np.testing.assert_array_equal(full["E_a"], recs["E_a"])
+    assert np.any(full["q0"])
+    ptsg.pt_free(ctx)
