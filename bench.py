@@ -46,7 +46,8 @@ def pmc_traffic(preset, mapping, expected_hash):
     """HBM bytes per overrelaxation launch from the committed rocprofv3 --pmc
     summary of this preset, if it was taken on the current kernel source with
     the same mapping.  The summaries cover Gaussian couplings and the
-    checkerboard order; other variants report null."""
+    checkerboard order (bimodal couplings: the preset's "_bimodal" summary);
+    other variants report null."""
     try:
         text = open(PMC_SUMMARY.format(preset=preset)).read()
     except OSError:
@@ -306,7 +307,8 @@ def main():
                                            "cl_half_sweep_kernel<overrelax>" if mapping == "chain"
                                            else "half_sweep_kernel<overrelax>"),
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": (None if rows or bimodal else pmc_traffic(args.preset, mapping, kernel_hash())),
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": (None if rows else pmc_traffic(args.preset + ("_bimodal" if bimodal else ""), mapping,
+                                                           kernel_hash())),
                 "traffic_counters": "FETCH_SIZE + WRITE_SIZE per launch, calibrated on a plain copy: bytes between "
                                     "the L2 caches and the fabric, Infinity-Cache hits included (not HBM alone)",
                 "algorithmic_bytes_per_launch": bytes_per_su * su_per_launch,
