@@ -64,7 +64,7 @@ typedef enum {
     PT_ENOMEM = -2,       /* workspace too small or allocation failed */
     PT_EDEVICE = -3,      /* HIP runtime error (message holds its string) */
     PT_ESTATE = -4,       /* call not valid in the context's state */
-    PT_EUNSUPPORTED = -5  /* valid but not supported by this build */
+    PT_EUNSUPPORTED = -5  /* valid but not supported by this library */
 } pt_status;
 
 /* Measurement selection bits for pt_measure. */

@@ -1,6 +1,6 @@
 """The Schwinger-Dyson identity of appendix A.4 on the GPU's own runs: in
 equilibrium, averaged over the lattice, 2T <s.h> - <h^2 - (s.h)^2> = 0 at
-every temperature.  The paper uses it to judge its random numbers; here it
+every temperature.  The paper uses it to test its random numbers; here it
 checks the heat-bath draws (Philox, the inverse CDF, the frame) and the
 tempering together, in every mapping, on the Gaussian and the bimodal
 couplings.  The same data evaluated at a temperature off by 5 % must fail,
