@@ -1415,7 +1415,7 @@ static pt_status build_program(pt_ctx *c, int n_hb, int n_or, pt_ctx::Program &g
         for (const auto &q : seqs)
             if (ph < q.size()) {
                 g.desc.push_back(q[ph]);
-                blocks += q[ph].n_blocks;
+                blocks += static_cast<int64_t>(q[ph].gx) * q[ph].gy * q[ph].gz;
             }
         if (blocks > (int64_t(1) << 30)) return fail(PT_EINVAL, "persistent step: a phase has too many workgroups");
         g.blocks.push_back(static_cast<int>(blocks));
