@@ -7,8 +7,11 @@
 // and the spins are written back once.  Small lattices are otherwise bound
 // by launch latency: a half-sweep of one L = 16 chain is 2048 updates.
 // Couplings come from the packed six-matrix layout (L2 resident at these
-// sizes); the field order and the update rules are the ones of the other
-// mappings, so the spins are bit-identical to theirs.
+// sizes); when every thread owns at most one site of each colour (N/2 <=
+// kRsRegSites, L <= 10) the 108 coefficients of its two sites are loaded
+// into registers once per step instead of once per half-sweep.  The field
+// order and the update rules are the ones of the other mappings, so the
+// spins are bit-identical to theirs.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -38,7 +41,13 @@ __device__ __forceinline__ void rs_neighbours(int p, int L, int colour, int (&id
     site = 2 * xh + par + L * row;
 }
 
-__global__ __launch_bounds__(kRsMaxBlock) void resident_step_kernel(RsParams P)
+// Largest half-lattice whose coefficients stay in registers: one site of
+// each colour per thread, 108 floats, in workgroups of at most 512 threads
+// (two waves per SIMD leave 256 VGPRs to a lane).
+constexpr int kRsRegSites = 512;
+
+template <bool kRegCpl>
+__global__ __launch_bounds__(kRegCpl ? kRsRegSites : kRsMaxBlock) void resident_step_kernel(RsParams P)
 {
     extern __shared__ float lds[];  // [colour][component][H]
     const int item = blockIdx.x;    // chain of the class: sample P.samples[item / C], chain item % C
@@ -56,6 +65,15 @@ __global__ __launch_bounds__(kRsMaxBlock) void resident_step_kernel(RsParams P)
         beta = P.beta_of[chain];
     }
     const float *cpl = P.cpl + P.cpl_base[s];
+    // kRegCpl: the coefficients of site threadIdx.x of each colour
+    float Areg[2][54];
+    if constexpr (kRegCpl) {
+        const int p = threadIdx.x < H ? threadIdx.x : 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int m = 0; m < 54; ++m) Areg[c][m] = cpl[(static_cast<int64_t>(c) * 54 + m) * H + p];
+    }
     const int total = P.n_hb + P.n_or;
     const uint32_t hb0 = P.counters[0];
     double e_acc = 0.0;
@@ -63,6 +81,7 @@ __global__ __launch_bounds__(kRsMaxBlock) void resident_step_kernel(RsParams P)
     for (int n = 0; n < total; ++n) {
         const int kind = P.energy_only ? kEnergyOnly : (n < P.n_hb ? kHeatbath : kOverrelax);
         const uint32_t hb_sweep = hb0 + static_cast<uint32_t>(n);
+#pragma unroll
         for (int c = 0; c < 2; ++c) {
             const float *oth = lds + (1 - c) * 3 * H;
             float *own = lds + c * 3 * H;
@@ -79,7 +98,10 @@ __global__ __launch_bounds__(kRsMaxBlock) void resident_step_kernel(RsParams P)
                     sn[q][2] = oth[2 * H + idx[q]];
                 }
                 float h[3];
-                local_field(sn, [&](int q, int a, int b) { return A[static_cast<int64_t>(q * 9 + a * 3 + b) * H + p]; }, h);
+                local_field(sn, [&](int q, int a, int b) {
+                    if constexpr (kRegCpl) return Areg[c][q * 9 + a * 3 + b];
+                    else return A[static_cast<int64_t>(q * 9 + a * 3 + b) * H + p];
+                }, h);
                 float sx, sy, sz;
                 if (kind == kHeatbath) {
                     const uint4 w = philox10(make_uint4(static_cast<uint32_t>(site), hb_sweep,
@@ -130,7 +152,9 @@ int rs_block(int L)
 hipError_t launch_resident_step(const RsParams &p, int n_chains, hipStream_t st, const LaunchTiming &t)
 {
     const uint32_t lds = static_cast<uint32_t>(sizeof(float) * 6 * static_cast<size_t>(p.H));
-    return launch_kernel(resident_step_kernel, dim3(n_chains), dim3(rs_block(p.L)), lds, st, t, p);
+    if (p.H <= kRsRegSites)   // one site of each colour per thread: rs_block(L) >= H
+        return launch_kernel(resident_step_kernel<true>, dim3(n_chains), dim3(rs_block(p.L)), lds, st, t, p);
+    return launch_kernel(resident_step_kernel<false>, dim3(n_chains), dim3(rs_block(p.L)), lds, st, t, p);
 }
 
 }  // namespace ptsg
