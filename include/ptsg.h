@@ -255,8 +255,9 @@ pt_status pt_measure(pt_ctx *ctx, unsigned what, pt_meas *out, size_t cap, size_
  * owns, asynchronously on the context's stream.  No allocation, no host copy,
  * no synchronisation.  The plane partials go to a fixed 8 MB device array of
  * the library (one per device, held until the process ends; records are
- * processed in chunks that fit it, so any batch pt_init_batch accepts fits),
- * and chain-lane samples are read in place.  Every call on one device shares
+ * processed in chunks that fit it, so any batch pt_init_batch accepts fits);
+ * chain-lane samples are copied to the site-lane layout in the context's own
+ * staging buffer first, as pt_measure does.  Every call on one device shares
  * that array: calls that overlap on one device (different streams, threads
  * or contexts) race.  PT_ENOMEM if cap is below the record count; the other
  * errors as pt_measure's.  The records equal pt_measure's. */

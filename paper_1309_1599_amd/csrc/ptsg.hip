@@ -1669,16 +1669,44 @@ pt_status pt_measure_noalloc(pt_ctx *c, unsigned what, pt_meas *d_out, size_t ca
     m.Lmax = P.Lmax;
     m.what = what;
     m.out = d_out;
-    m.stage = nullptr;
-    m.stage_sample = -1;
-    for (int r0 = 0; r0 < P.n_records; r0 += chunk) {
-        const int n = std::min(chunk, P.n_records - r0);
-        m.rec0 = r0;
-        m.part_rec0 = r0;
-        m.n_records = r0 + n;
-        PT_HIP(launch_measure_records(m, n, P.Lmax, c->stream));
-        PT_HIP(launch_measure_finalize(m, c->stream));
+    m.stage = c->stage;
+    // records [a, b) (lattices up to L), in chunks whose partials fit the
+    // scratch array; `staged` names the chain-lane sample whose chains sit in
+    // the context's staging buffer (-1: none)
+    auto run_range = [&](int a, int b, int L, int staged) -> hipError_t {
+        for (int r0 = a; r0 < b; r0 += chunk) {
+            MeasParams q = m;
+            q.stage_sample = staged;
+            q.rec0 = r0;
+            q.part_rec0 = r0;
+            q.n_records = std::min(r0 + chunk, b);
+            hipError_t e = launch_measure_records(q, q.n_records - r0, L, c->stream);
+            if (e == hipSuccess) e = launch_measure_finalize(q, c->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    // As in pt_measure: runs of site-lane samples in place; a chain-lane
+    // sample (64 chains interleaved per site) first copied to the site-lane
+    // layout in the context's staging buffer (part of its workspace: nothing
+    // is allocated), so the record kernels read whole component rows.
+    const bool planes = what & (PT_M_OVERLAP | PT_M_CHIRAL | PT_M_SD);
+    int first = 0, run_start = 0, run_L = 0;
+    for (int s = 0; s < P.S; ++s) {
+        const int n = P.T[s] * P.R * (P.R - 1) / 2;
+        if (P.lanes[s] != 1 && planes) {
+            PT_HIP(run_range(run_start, first, run_L, -1));
+            const int L = P.L[s];
+            PT_HIP(launch_cl_to_sl(c->spins, P.spin_base[s], L * L * L / 2, P.R * P.T[s], c->stage, c->stream));
+            PT_HIP(run_range(first, first + n, L, s));
+            run_start = first + n;
+            run_L = 0;
+        } else {
+            run_L = std::max(run_L, P.L[s]);
+        }
+        first += n;
     }
+    PT_HIP(run_range(run_start, first, run_L, -1));
     return PT_OK;
 }
 

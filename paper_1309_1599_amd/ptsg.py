@@ -139,8 +139,13 @@ class PtContext:
         return sum(T * self.n_replicas for T in self.n_temps)
 
     def __del__(self):
-        if getattr(self, "ptr", None) is not None and self.ptr.value:
-            pt_free(self)
+        # at interpreter exit the module's globals may already be gone: the
+        # process is ending and the driver releases the device memory
+        if getattr(self, "ptr", None) is not None and self.ptr.value and pt_free is not None:
+            try:
+                pt_free(self)
+            except Exception:
+                pass
 
 
 def _f32(a):
