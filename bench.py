@@ -163,7 +163,8 @@ def mixed_cpu_baseline(Ls, cpl, temps, R, seed, n_hb, n_or, or_l):
     }
 
 
-def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, warmup, timing=True):
+def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, warmup, timing=True,
+        what=None):
     """Time `steps` steps after `warmup`; optionally a second pass with
     kernel-stamped events for the kernel durations."""
     ctx = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=flags)
@@ -176,7 +177,7 @@ def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, w
         ptsg.pt_step(ctx, n_hb, n_or)
         ptsg.pt_swap(ctx)
         if every and (t + 1) % every == 0:
-            ptsg.pt_measure(ctx, ptsg.PT_M_ALL)
+            ptsg.pt_measure(ctx, ptsg.PT_M_ALL if what is None else what)
 
     for t in range(warmup):
         step(t)
@@ -253,6 +254,10 @@ def main():
     # the paper's step: 1 HB + L OR + PT, each sample with its own L
     n_or = (ptsg.PT_OR_L if mixed else Ls[0]) if p["n_or"] is None else p["n_or"]
     every = p["measure_every"]
+    bits = {"overlap": ptsg.PT_M_OVERLAP, "chiral": ptsg.PT_M_CHIRAL, "sd": ptsg.PT_M_SD}
+    what = ptsg.PT_M_ENERGY
+    for m in p.get("measure", ("overlap", "chiral", "sd")):
+        what |= bits[m]
     flags = {"auto": 0, "tuned": ptsg.PT_F_AUTOTUNE, "site": ptsg.PT_F_SITE_LANES,
              "chain": ptsg.PT_F_CHAIN_LANES, "resident": ptsg.PT_F_RESIDENT}[args.mapping]
     if not args.no_graphs:
@@ -274,7 +279,7 @@ def main():
     del a, b
 
     wall, su_per_step, kt, maps = run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every,
-                                      args.steps, args.warmup)
+                                      args.steps, args.warmup, what=what)
     mapping = maps[0]
     ps_per_su = wall / (args.steps * su_per_step) * 1e12
     n_chains = sum(R * len(t) for t in temps)
@@ -348,7 +353,8 @@ def main():
                         + ("bimodal couplings (D = 0.5, one byte per bond); step" if bimodal
                            else "Gaussian 3x3 couplings; step") + f" = {n_hb} HB + "
                         + ("L" if n_or == ptsg.PT_OR_L else str(n_or)) + " OR sweeps + PT pass"
-                        + (f", measurement every {every} steps" if every else ""),
+                        + (f", measurement ({'+'.join(p.get('measure', ('overlap', 'chiral', 'sd')))}) "
+                           f"every {every} steps" if every else ""),
             "L": L if not mixed else sorted(set(Ls)), "samples": len(Ls),
             "temperatures": len(temps[0]) if not mixed else sorted({len(t) for t in temps}),
             "replicas": R, "spin_updates_per_step": su_per_step,
@@ -373,7 +379,7 @@ def main():
         # the same workload as one persistent launch per step
         pf = (flags & ~(ptsg.PT_F_RESIDENT | ptsg.PT_F_AUTOTUNE | ptsg.PT_F_GRAPHS)) | ptsg.PT_F_PERSISTENT
         w, su, _, m = run(ptsg, torch, Ls, cpl, temps, R, seed, pf, n_hb, n_or, every, args.steps, 1,
-                          timing=False)
+                          timing=False, what=what)
         ps = w / (args.steps * su) * 1e12
         result["persistent_step"] = {"value": round(ps, 4), "unit": "ps/SU", "mapping": m[0] + " lanes",
                                      "ratio_to_value": round(ps / ps_per_su, 3),
@@ -403,7 +409,7 @@ def main():
     elif not args.no_plain and not rows:   # the plain form is checkerboard only
         pflags = ptsg.PT_F_PLAIN | (0 if args.no_graphs else ptsg.PT_F_GRAPHS) | (ptsg.PT_F_BIMODAL if bimodal else 0)
         w, su, _, _ = run(ptsg, torch, Ls, cpl, temps, R, seed, pflags, n_hb, n_or, every, 1, 1,
-                          timing=False)
+                          timing=False, what=what)
         plain = w / su * 1e12
         result["plain_single_chain"] = {"value": round(plain, 3), "unit": "ps/SU",
                                         "speedup_of_value": round(plain / ps_per_su, 3),

@@ -62,18 +62,21 @@ def random_spins(N, seed, *stream):
 
 # Workload presets (lattice sizes, ensemble shape, step composition).  The
 # step is n_hb heat-bath + n_or overrelaxation sweeps + one tempering pass;
-# the paper's MCS has n_or = L (Sec. III).
+# the paper's MCS has n_or = L (Sec. III).  `measure` lists what a
+# measurement step records (energies always): the L = 8 workload takes
+# E, q(0) and q(k_min) every step, the L = 64 one the q(k_min) Fourier sums
+# and the chirality every 10 steps.
 C5_TEMPS = {8: 16, 12: 18, 16: 20, 24: 24, 32: 28, 48: 32}
 
 PRESETS = {
     "L8": dict(L=[8], temps=("linear", 0.5, 2.0, 8), R=2, n_hb=1, n_or=8, measure_every=1,
-               seed=130915991),
+               measure=("overlap",), seed=130915991),
     "L16": dict(L=[16], temps=("geometric", 0.5, 2.0, 16), R=2, n_hb=1, n_or=16,
                 measure_every=0, seed=130915992),
     "L32x64": dict(L=[32] * 64, temps=("geometric", 0.6, 1.8, 24), R=4, n_hb=1, n_or=32,
                    measure_every=0, seed=130915993),
     "L64x8": dict(L=[64] * 8, temps=("geometric", 0.6, 1.6, 32), R=4, n_hb=1, n_or=64,
-                  measure_every=10, seed=130915994),
+                  measure_every=10, measure=("overlap", "chiral"), seed=130915994),
     "mixedL": dict(L=[L for L in (8, 12, 16, 24, 32, 48) for _ in range(16)],
                    temps=("geometric", 0.6, 1.8, None), R=2, n_hb=1, n_or=None,
                    measure_every=0, seed=130915995),
