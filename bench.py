@@ -173,22 +173,31 @@ def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, w
     su_per_step = sum((n_hb + (L if n_or == ptsg.PT_OR_L else n_or)) * R * len(t) * L ** 3
                       for L, t in zip(Ls, temps))
 
+    what = ptsg.PT_M_ALL if what is None else what
+
     def step(t):
         ptsg.pt_step(ctx, n_hb, n_or)
         ptsg.pt_swap(ctx)
         if every and (t + 1) % every == 0:
-            ptsg.pt_measure(ctx, ptsg.PT_M_ALL if what is None else what)
+            ptsg.pt_measure(ctx, what)
 
-    for t in range(warmup):
-        step(t)
+    # The timed steps run through pt_run: whole steps (sweeps, tempering and,
+    # every `every` steps, the measurement) replayed as captured graphs, the
+    # records written to a device buffer and copied to the host once, inside
+    # the timed region.
+    n_rec = ctx.n_records
+    sets = max(steps, warmup) // every if every else 0
+    buf = torch.empty(max(1, sets * n_rec * ptsg.MEAS_DTYPE.itemsize), dtype=torch.uint8, device="cuda")
+    ptsg.pt_run(ctx, warmup, n_hb, n_or, every, what, buf.data_ptr(), sets * n_rec)
     ptsg.pt_sync(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for t in range(steps):
-        step(t)
+    ptsg.pt_run(ctx, steps, n_hb, n_or, every, what, buf.data_ptr(), sets * n_rec)
     ptsg.pt_sync(ctx)
+    records = buf.cpu()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    del records
     kt = None
     if timing:
         # Kernel durations: the same steps again with the dispatches stamping

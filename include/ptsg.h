@@ -249,6 +249,20 @@ pt_status pt_swap(pt_ctx *ctx);
  * PT_M_CHIRAL need n_replicas >= 2 (PT_ESTATE).  Synchronous. */
 pt_status pt_measure(pt_ctx *ctx, unsigned what, pt_meas *out, size_t cap, size_t *n_out);
 
+/* Whole Monte Carlo steps (Sec. III: the sweeps of one step, then one
+ * tempering pass, and every `every` steps a measurement): n_steps times
+ * pt_step(n_hb, n_or) + pt_swap, and after steps every, 2*every, ... the
+ * records of pt_measure(what), measurement k written to
+ * d_out[k * n_records ...], d_out a DEVICE array of cap pt_meas the caller
+ * owns (cap >= (n_steps / every) * n_records; every = 0: no measurement,
+ * d_out may be NULL).  With PT_F_GRAPHS each kind of step (with and without
+ * a measurement) is captured once as one hipGraph -- sweeps, tempering and
+ * measurement kernels together -- and replayed, so a step costs one graph
+ * launch on the host; the results equal those of the separate calls.
+ * Asynchronous.  Errors as pt_step, pt_measure; PT_ENOMEM if cap is short. */
+pt_status pt_run(pt_ctx *ctx, int n_steps, int n_hb, int n_or, int every, unsigned what, pt_meas *d_out,
+                 size_t cap);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the records of
  * pt_measure, written to d_out, a DEVICE array of cap pt_meas the caller

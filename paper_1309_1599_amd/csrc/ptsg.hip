@@ -427,6 +427,8 @@ struct pt_ctx {
     bool row_or = false;              // PT_F_ROW_OR: overrelaxation sweeps in the row order
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
+    // pt_run: (n_hb, n_or, measurement bits or ~0 for none) -> a whole step
+    std::map<std::tuple<int, int, unsigned>, hipGraphExec_t> run_graphs;
     // PT_F_PERSISTENT: one program per (n_hb, n_or), in library-owned memory
     struct Program {
         std::vector<StepDesc> desc;
@@ -1391,6 +1393,33 @@ static pt_status queue_step(pt_ctx *c, int n_hb, int n_or)
     return PT_OK;
 }
 
+// Capture what `queue` enqueues on the context's stream as a graph, on a
+// private default-priority stream, and instantiate it.  The random-number
+// counters live in device memory and are advanced by kernels inside the
+// work, so every replay draws fresh numbers; nothing captured is a memset.
+extern "C++" template <class Queue>
+static pt_status capture_graph(pt_ctx *c, Queue queue, hipGraphExec_t *out)
+{
+    if (!c->capture_stream) PT_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    const hipError_t eb = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (eb != hipSuccess) return fail(PT_EDEVICE, std::string("stream capture: ") + hipGetErrorString(eb));
+    hipStream_t user = c->stream;
+    c->stream = c->capture_stream;
+    const pt_status st = queue();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+    c->stream = user;
+    if (st != PT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(PT_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(PT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    return PT_OK;
+}
+
 // PT_F_PERSISTENT: the step's descriptors, class by class, merged into
 // phases: phase i holds the i-th descriptor of every class whose sequence
 // is that long (classes share no data, and a descriptor depends at most on
@@ -1495,23 +1524,8 @@ pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
         // once on a private stream, then replay it on the context's stream.
         auto it = c->step_graphs.find({n_hb, n_or});
         if (it == c->step_graphs.end()) {
-            if (!c->capture_stream) PT_HIP(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-            hipStream_t user = c->stream;
-            c->stream = c->capture_stream;
-            hipGraph_t graph = nullptr;
-            PT_HIP(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal));
-            st = queue_step(c, n_hb, n_or);
-            const hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
-            c->stream = user;
-            if (st != PT_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return st;
-            }
-            if (e != hipSuccess) return fail(PT_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
             hipGraphExec_t exec = nullptr;
-            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (ei != hipSuccess) return fail(PT_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+            if ((st = capture_graph(c, [&] { return queue_step(c, n_hb, n_or); }, &exec)) != PT_OK) return st;
             it = c->step_graphs.emplace(std::make_pair(n_hb, n_or), exec).first;
         }
         PT_HIP(hipGraphLaunch(it->second, c->stream));
@@ -1520,10 +1534,9 @@ pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
     return PT_OK;
 }
 
-pt_status pt_swap(pt_ctx *c)
+// Queue one tempering pass and the advance of the pass counter.
+static pt_status queue_swap(pt_ctx *c)
 {
-    pt_status st = check_ctx(c);
-    if (st != PT_OK) return st;
     SwapParams p{};
     p.perm = c->perm;
     p.slot_of = c->slot_of;
@@ -1541,25 +1554,23 @@ pt_status pt_swap(pt_ctx *c)
     p.key1 = static_cast<uint32_t>(c->seed >> 32);
     PT_HIP(launch_swap(p, c->stream));
     PT_HIP(launch_advance_counters(c->counters, 0u, 1u, c->stream));
+    return PT_OK;
+}
+
+pt_status pt_swap(pt_ctx *c)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if ((st = queue_swap(c)) != PT_OK) return st;
     c->pt_passes += 1;
     return PT_OK;
 }
 
-pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t *n_out)
+// Queue the record kernels of every record into the context's device
+// records (c->meas); no copy, no wait.
+static pt_status queue_measure(pt_ctx *c, unsigned what)
 {
-    pt_status st = check_ctx(c);
-    if (st != PT_OK) return st;
-    if (what & ~static_cast<unsigned>(PT_M_ALL)) return fail(PT_EINVAL, "unknown measurement bits");
     const Plan &P = c->plan;
-    if ((what & (PT_M_OVERLAP | PT_M_CHIRAL)) && P.R < 2)
-        return fail(PT_ESTATE, "overlap and chirality need n_replicas >= 2");
-    if (n_out) *n_out = static_cast<size_t>(P.n_records);
-    if (P.n_records == 0) return PT_OK;
-    if (!out && cap == 0) return PT_OK;   // size query
-    if (!out) return fail(PT_EINVAL, "output buffer is NULL");
-    if (cap < static_cast<size_t>(P.n_records))
-        return fail(PT_ENOMEM, "output holds " + std::to_string(cap) + " records, " +
-                                   std::to_string(P.n_records) + " needed");
     MeasParams m{};
     m.spins = c->spins;
     m.cpls = c->cpls;
@@ -1617,6 +1628,25 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
         PT_HIP(flush(first));
         PT_HIP(launch_measure_finalize(m, c->stream));
     }
+    return PT_OK;
+}
+
+pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t *n_out)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (what & ~static_cast<unsigned>(PT_M_ALL)) return fail(PT_EINVAL, "unknown measurement bits");
+    const Plan &P = c->plan;
+    if ((what & (PT_M_OVERLAP | PT_M_CHIRAL)) && P.R < 2)
+        return fail(PT_ESTATE, "overlap and chirality need n_replicas >= 2");
+    if (n_out) *n_out = static_cast<size_t>(P.n_records);
+    if (P.n_records == 0) return PT_OK;
+    if (!out && cap == 0) return PT_OK;   // size query
+    if (!out) return fail(PT_EINVAL, "output buffer is NULL");
+    if (cap < static_cast<size_t>(P.n_records))
+        return fail(PT_ENOMEM, "output holds " + std::to_string(cap) + " records, " +
+                                   std::to_string(P.n_records) + " needed");
+    if ((st = queue_measure(c, what)) != PT_OK) return st;
     PT_HIP(hipMemcpyAsync(out, c->meas, sizeof(pt_meas) * P.n_records, hipMemcpyDeviceToHost,
                           c->stream));
     PT_HIP(hipStreamSynchronize(c->stream));
@@ -1707,6 +1737,63 @@ pt_status pt_measure_noalloc(pt_ctx *c, unsigned what, pt_meas *d_out, size_t ca
         first += n;
     }
     PT_HIP(run_range(run_start, first, run_L, -1));
+    return PT_OK;
+}
+
+pt_status pt_run(pt_ctx *c, int n_steps, int n_hb, int n_or, int every, unsigned what, pt_meas *d_out,
+                 size_t cap)
+{
+    pt_status st = check_ctx(c);
+    if (st != PT_OK) return st;
+    if (n_steps < 0 || every < 0) return fail(PT_EINVAL, "n_steps and every must be >= 0");
+    if (n_hb < 0 || (n_or < 0 && n_or != PT_OR_L))
+        return fail(PT_EINVAL, "n_hb must be >= 0 and n_or >= 0 or PT_OR_L");
+    if (what & ~static_cast<unsigned>(PT_M_ALL)) return fail(PT_EINVAL, "unknown measurement bits");
+    const Plan &P = c->plan;
+    const int64_t n_meas = (every > 0 && P.n_records > 0) ? n_steps / every : 0;
+    if (n_meas > 0) {
+        if ((what & (PT_M_OVERLAP | PT_M_CHIRAL)) && P.R < 2)
+            return fail(PT_ESTATE, "overlap and chirality need n_replicas >= 2");
+        if (!d_out) return fail(PT_EINVAL, "output buffer is NULL");
+        if (cap < static_cast<size_t>(n_meas) * P.n_records)
+            return fail(PT_ENOMEM, "output holds " + std::to_string(cap) + " records, " +
+                                       std::to_string(n_meas * P.n_records) + " needed");
+    }
+    const bool sweeps = n_hb > 0 || n_or != 0;
+    // one Monte Carlo step, and one with a measurement after it
+    auto queue = [&](bool measure) -> pt_status {
+        pt_status q = PT_OK;
+        if (sweeps) q = c->persistent ? persistent_step(c, n_hb, n_or) : queue_step(c, n_hb, n_or);
+        if (q == PT_OK) q = queue_swap(c);
+        if (q == PT_OK && measure) q = queue_measure(c, what);
+        return q;
+    };
+    // the persistent step builds its work list on first use, and kernel
+    // timing needs every launch on its own: both run the steps one by one
+    const bool graphs = c->use_graphs && !c->profiling && !c->persistent;
+    int64_t k = 0;
+    for (int t = 0; t < n_steps; ++t) {
+        const bool measure = n_meas > 0 && (t + 1) % every == 0;
+        if (graphs) {
+            const auto key = std::make_tuple(n_hb, n_or, measure ? what : ~0u);
+            auto it = c->run_graphs.find(key);
+            if (it == c->run_graphs.end()) {
+                hipGraphExec_t exec = nullptr;
+                if ((st = capture_graph(c, [&] { return queue(measure); }, &exec)) != PT_OK) return st;
+                it = c->run_graphs.emplace(key, exec).first;
+            }
+            PT_HIP(hipGraphLaunch(it->second, c->stream));
+        } else if ((st = queue(measure)) != PT_OK) {
+            return st;
+        }
+        c->hb_sweeps += n_hb;
+        c->pt_passes += 1;
+        if (measure) {
+            PT_HIP(hipMemcpyAsync(d_out + k * P.n_records, c->meas, sizeof(pt_meas) * P.n_records,
+                                  hipMemcpyDeviceToDevice, c->stream));
+            ++k;
+        }
+    }
     return PT_OK;
 }
 
@@ -2056,6 +2143,7 @@ void pt_free(pt_ctx *c)
         (void)hipEventDestroy(e.b);
     }
     for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &g : c->run_graphs) (void)hipGraphExecDestroy(g.second);
     for (auto &g : c->programs) (void)hipFree(g.second.mem);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);

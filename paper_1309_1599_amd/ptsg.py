@@ -34,7 +34,7 @@ assert MEAS_DTYPE.itemsize == 744
 
 # Every symbol the C ABI exports (include/ptsg.h).
 EXPORTS = ["pt_init", "pt_workspace_size", "pt_init_batch", "pt_step", "pt_swap", "pt_measure",
-           "pt_measure_noalloc",
+           "pt_measure_noalloc", "pt_run",
            "pt_get_spins", "pt_set_spins", "pt_get_perm", "pt_get_perms", "pt_get_energy", "pt_get_counters",
            "pt_set_stream", "pt_sync", "pt_profile", "pt_kernel_time", "pt_get_mapping", "pt_get_tile",
            "pt_save", "pt_load", "pt_free", "pt_last_error"]
@@ -81,6 +81,7 @@ def load_library(path=LIB_PATH):
         "pt_swap": (i, [vp]),
         "pt_measure": (i, [vp, C.c_uint, vp, sz, C.POINTER(sz)]),
         "pt_measure_noalloc": (i, [vp, C.c_uint, vp, sz]),
+        "pt_run": (i, [vp, i, i, i, i, C.c_uint, vp, sz]),
         "pt_get_spins": (i, [vp, i, i, i, C.POINTER(C.c_float)]),
         "pt_set_spins": (i, [vp, i, i, i, C.POINTER(C.c_float)]),
         "pt_get_perm": (i, [vp, i, i, C.POINTER(C.c_int32)]),
@@ -222,6 +223,14 @@ def pt_measure(ctx, what=PT_M_ALL):
     _check(load_library().pt_measure(ctx.ptr, int(what), out.ctypes.data_as(C.c_void_p),
                                      len(out), C.byref(n)))
     return out[: n.value]
+
+
+def pt_run(ctx, n_steps, n_hb, n_or, every=0, what=PT_M_ALL, d_out=0, cap=0):
+    """n_steps whole steps (sweeps + tempering, a measurement every `every`
+    steps into the device array at address d_out with room for cap records);
+    asynchronous."""
+    _check(load_library().pt_run(ctx.ptr, int(n_steps), int(n_hb), int(n_or), int(every), int(what),
+                                 C.c_void_p(int(d_out)) if d_out else None, int(cap)))
 
 
 def pt_measure_noalloc(ctx, what, d_out, cap):
