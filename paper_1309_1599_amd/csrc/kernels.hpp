@@ -135,6 +135,15 @@ struct EnergyParams {
     double *E;
 };
 
+// Where the records of the next measurement go when a run of whole steps is
+// replayed as graphs: base + k * stride, k advanced on the device after
+// every measurement (so the captured kernels need no new arguments).
+struct RecordCursor {
+    void *base;                  // device pt_meas array of the caller
+    uint64_t k;                  // measurements written so far
+    uint64_t stride;             // records per measurement
+};
+
 struct MeasParams {
     const float *spins;
     const float *cpls;           // site-major couplings
@@ -150,6 +159,7 @@ struct MeasParams {
     int part_rec0;               // record whose partials sit at the start of `part`
     unsigned what;
     void *out;                   // device pt_meas[n_records]
+    RecordCursor *cursor;        // non-null: write to cursor->base + cursor->k * stride instead
     // Sample `stage_sample` (-1: none) is read from `stage`, a site-lane
     // copy of its chains ([chain][colour][component][H]) instead of `spins`.
     const float *stage;
@@ -235,6 +245,9 @@ hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, 
 // [rec0, n_records).
 hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st);
 hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st);
+// One lane: cursor = {base, 0, stride}; cursor->k += 1.
+hipError_t launch_set_cursor(RecordCursor *cursor, void *base, uint64_t stride, hipStream_t st);
+hipError_t launch_advance_cursor(RecordCursor *cursor, hipStream_t st);
 // Copy the chains of a chain-lane sample into the site-lane layout (the
 // measurement kernels then read each component plane coalesced).
 hipError_t launch_cl_to_sl(const float *spins, int64_t base, int H, int C, float *stage, hipStream_t st);

@@ -221,7 +221,9 @@ __global__ void finalize_kernel(MeasParams P)
     const double invN = 1.0 / (static_cast<double>(L) * L * L);
     const double *cw = P.twid + P.twid_base[s], *sw = cw + L;
     const double *part = P.part + static_cast<int64_t>(rec - P.part_rec0) * P.Lmax * kPlaneQ;
-    pt_meas &m = static_cast<pt_meas *>(P.out)[rec];
+    pt_meas *out = P.cursor ? static_cast<pt_meas *>(P.cursor->base) + P.cursor->k * P.cursor->stride
+                            : static_cast<pt_meas *>(P.out);
+    pt_meas &m = out[rec];
     m.sample = s;
     m.tslot = k;
     m.rep_a = ra;
@@ -298,7 +300,33 @@ __global__ __launch_bounds__(256) void cl_to_sl_kernel(const float *spins, int64
     }
 }
 
+__global__ void set_cursor_kernel(RecordCursor *cursor, void *base, uint64_t stride)
+{
+    if (threadIdx.x == 0) {
+        cursor->base = base;
+        cursor->k = 0;
+        cursor->stride = stride;
+    }
+}
+
+__global__ void advance_cursor_kernel(RecordCursor *cursor)
+{
+    if (threadIdx.x == 0) cursor->k += 1;
+}
+
 }  // namespace
+
+hipError_t launch_set_cursor(RecordCursor *cursor, void *base, uint64_t stride, hipStream_t st)
+{
+    hipLaunchKernelGGL(set_cursor_kernel, dim3(1), dim3(64), 0, st, cursor, base, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance_cursor(RecordCursor *cursor, hipStream_t st)
+{
+    hipLaunchKernelGGL(advance_cursor_kernel, dim3(1), dim3(64), 0, st, cursor);
+    return hipGetLastError();
+}
 
 hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st)
 {

@@ -41,6 +41,7 @@ pt_status fail(pt_status st, const std::string &msg)
 
 constexpr size_t kAlign = 256;
 
+
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // One lattice class: samples sharing L, the number of temperatures and the
@@ -72,7 +73,7 @@ struct Plan {
     size_t off_spins = 0, off_cpls = 0, off_cpl6 = 0, off_slot = 0, off_beta_of = 0, off_E = 0,
            off_perm = 0, off_betas = 0, off_epart = 0, off_twid = 0, off_meta = 0, off_rec = 0,
            off_mpart = 0, off_meas = 0, off_classes = 0, off_items = 0, off_stage = 0, off_counters = 0,
-           off_bmD = 0, off_bmtab = 0,
+           off_bmD = 0, off_bmtab = 0, off_cursor = 0,
            bytes = 0;
 };
 
@@ -367,6 +368,7 @@ Plan make_plan(const pt_batch_desc *d, const std::vector<Tile> *forced = nullptr
     p.off_bmD = take(sizeof(float) * p.S);
     // bimodal: per sample the matrix of each of the 128 codes (chain lanes)
     p.off_bmtab = take(sizeof(float) * ((d->flags & PT_F_BIMODAL) ? 128 * 9 * static_cast<size_t>(p.S) : 1));
+    p.off_cursor = take(sizeof(RecordCursor));
     p.bytes = o;
     return p;
 }
@@ -423,12 +425,17 @@ struct pt_ctx {
     uint32_t *counters = nullptr;     // device: heat-bath sweeps, PT passes
     float *bm_D = nullptr;            // device, per sample: D of the bimodal family (PT_F_BIMODAL)
     float *bm_table = nullptr;        // device, per sample: [128][9] matrix of each bond code
+    RecordCursor *cursor = nullptr;   // device: where pt_run's next measurement goes
     bool use_graphs = false;
     bool row_or = false;              // PT_F_ROW_OR: overrelaxation sweeps in the row order
     hipStream_t capture_stream = nullptr;
     std::map<std::pair<int, int>, hipGraphExec_t> step_graphs;
-    // pt_run: (n_hb, n_or, measurement bits or ~0 for none) -> a whole step
-    std::map<std::tuple<int, int, unsigned>, hipGraphExec_t> run_graphs;
+    // pt_run: (n_hb, n_or, measurement bits or ~0 for none) -> graphs of one
+    // step without and with a measurement after it
+    struct RunGraphs {
+        hipGraphExec_t one[2] = {nullptr, nullptr};
+    };
+    std::map<std::tuple<int, int, unsigned>, RunGraphs> run_graphs;
     // PT_F_PERSISTENT: one program per (n_hb, n_or), in library-owned memory
     struct Program {
         std::vector<StepDesc> desc;
@@ -1011,6 +1018,7 @@ static pt_status init_batch(pt_ctx **out, const pt_batch_desc *d, const std::vec
     c->counters = reinterpret_cast<uint32_t *>(w + P.off_counters);
     c->bm_D = reinterpret_cast<float *>(w + P.off_bmD);
     c->bm_table = reinterpret_cast<float *>(w + P.off_bmtab);
+    c->cursor = reinterpret_cast<RecordCursor *>(w + P.off_cursor);
     c->use_graphs = (d->flags & PT_F_GRAPHS) != 0;
     c->row_or = (d->flags & PT_F_ROW_OR) != 0;
     c->persistent = (d->flags & PT_F_PERSISTENT) != 0;
@@ -1568,10 +1576,11 @@ pt_status pt_swap(pt_ctx *c)
 
 // Queue the record kernels of every record into the context's device
 // records (c->meas); no copy, no wait.
-static pt_status queue_measure(pt_ctx *c, unsigned what)
+static pt_status queue_measure(pt_ctx *c, unsigned what, bool to_cursor = false)
 {
     const Plan &P = c->plan;
     MeasParams m{};
+    m.cursor = to_cursor ? c->cursor : nullptr;
     m.spins = c->spins;
     m.cpls = c->cpls;
     m.rec = c->rec;
@@ -1628,6 +1637,7 @@ static pt_status queue_measure(pt_ctx *c, unsigned what)
         PT_HIP(flush(first));
         PT_HIP(launch_measure_finalize(m, c->stream));
     }
+    if (to_cursor) PT_HIP(launch_advance_cursor(c->cursor, c->stream));
     return PT_OK;
 }
 
@@ -1760,40 +1770,37 @@ pt_status pt_run(pt_ctx *c, int n_steps, int n_hb, int n_or, int every, unsigned
                                        std::to_string(n_meas * P.n_records) + " needed");
     }
     const bool sweeps = n_hb > 0 || n_or != 0;
-    // one Monte Carlo step, and one with a measurement after it
-    auto queue = [&](bool measure) -> pt_status {
-        pt_status q = PT_OK;
-        if (sweeps) q = c->persistent ? persistent_step(c, n_hb, n_or) : queue_step(c, n_hb, n_or);
-        if (q == PT_OK) q = queue_swap(c);
-        if (q == PT_OK && measure) q = queue_measure(c, what);
-        return q;
+    // `n` Monte Carlo steps from step t0 on, each followed by a measurement
+    // when it is a multiple of `every`; records go through the device cursor
+    auto queue = [&](int t0, int n) -> pt_status {
+        for (int t = t0; t < t0 + n; ++t) {
+            pt_status q = PT_OK;
+            if (sweeps) q = c->persistent ? persistent_step(c, n_hb, n_or) : queue_step(c, n_hb, n_or);
+            if (q == PT_OK) q = queue_swap(c);
+            if (q == PT_OK && n_meas > 0 && (t + 1) % every == 0) q = queue_measure(c, what, true);
+            if (q != PT_OK) return q;
+        }
+        return PT_OK;
     };
+    if (n_steps == 0) return PT_OK;
+    if (n_meas > 0) PT_HIP(launch_set_cursor(c->cursor, d_out, static_cast<uint64_t>(P.n_records), c->stream));
     // the persistent step builds its work list on first use, and kernel
     // timing needs every launch on its own: both run the steps one by one
     const bool graphs = c->use_graphs && !c->profiling && !c->persistent;
-    int64_t k = 0;
-    for (int t = 0; t < n_steps; ++t) {
-        const bool measure = n_meas > 0 && (t + 1) % every == 0;
-        if (graphs) {
-            const auto key = std::make_tuple(n_hb, n_or, measure ? what : ~0u);
-            auto it = c->run_graphs.find(key);
-            if (it == c->run_graphs.end()) {
-                hipGraphExec_t exec = nullptr;
-                if ((st = capture_graph(c, [&] { return queue(measure); }, &exec)) != PT_OK) return st;
-                it = c->run_graphs.emplace(key, exec).first;
-            }
-            PT_HIP(hipGraphLaunch(it->second, c->stream));
-        } else if ((st = queue(measure)) != PT_OK) {
-            return st;
-        }
-        c->hb_sweeps += n_hb;
-        c->pt_passes += 1;
-        if (measure) {
-            PT_HIP(hipMemcpyAsync(d_out + k * P.n_records, c->meas, sizeof(pt_meas) * P.n_records,
-                                  hipMemcpyDeviceToDevice, c->stream));
-            ++k;
+    if (!graphs) {
+        if ((st = queue(0, n_steps)) != PT_OK) return st;
+    } else {
+        // graphs of one step, without and with a measurement after it
+        const unsigned mbits = n_meas > 0 ? what : ~0u;
+        hipGraphExec_t *g = c->run_graphs[std::make_tuple(n_hb, n_or, mbits)].one;
+        for (int t = 0; t < n_steps; ++t) {
+            const int m = n_meas > 0 && (t + 1) % every == 0;
+            if (!g[m] && (st = capture_graph(c, [&] { return queue(t, 1); }, &g[m])) != PT_OK) return st;
+            PT_HIP(hipGraphLaunch(g[m], c->stream));
         }
     }
+    c->hb_sweeps += static_cast<uint64_t>(n_hb) * n_steps;
+    c->pt_passes += static_cast<uint64_t>(n_steps);
     return PT_OK;
 }
 
@@ -2143,7 +2150,9 @@ void pt_free(pt_ctx *c)
         (void)hipEventDestroy(e.b);
     }
     for (auto &g : c->step_graphs) (void)hipGraphExecDestroy(g.second);
-    for (auto &g : c->run_graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &g : c->run_graphs)
+        for (hipGraphExec_t e : g.second.one)
+            if (e) (void)hipGraphExecDestroy(e);
     for (auto &g : c->programs) (void)hipFree(g.second.mem);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->own_ws && c->ws) (void)hipFree(c->ws);

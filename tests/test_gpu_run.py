@@ -72,6 +72,40 @@ def test_run_equals_separate_calls(flags):
     ptsg.pt_free(ref)
 
 
+@pytest.mark.parametrize("every", [1, 3])
+def test_run_many_short_steps(every):
+    """One L = 8 sample (resident): runs of 40, 17 and 3 steps, measuring
+    every step or every third, each record and the state equal to the
+    separate calls (the device record cursor keeps counting across the
+    replays of one call)."""
+    import torch
+    seed = 6300 + every
+    L, T, R = 8, 8, 2
+    temps = [inputs.linear_temps(0.5, 2.0, T)]
+    cpl = [inputs.gaussian_couplings(L, seed)]
+    run = ptsg.pt_init_batch([L], cpl, temps, R, seed, flags=ptsg.PT_F_GRAPHS)
+    ref = ptsg.pt_init_batch([L], cpl, temps, R, seed)
+    n_rec = run.n_records
+    what = ptsg.PT_M_OVERLAP | ptsg.PT_M_ENERGY
+    cap = 40 // every * n_rec
+    buf = torch.zeros(cap * ptsg.MEAS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    for call, n_steps in enumerate((40, 17, 3)):
+        ptsg.pt_run(run, n_steps, 1, L, every, what, buf.data_ptr(), cap)
+        ptsg.pt_sync(run)
+        got = np.frombuffer(buf.cpu().numpy().tobytes(), dtype=ptsg.MEAS_DTYPE)
+        k = 0
+        for t in range(n_steps):
+            ptsg.pt_step(ref, 1, L)
+            ptsg.pt_swap(ref)
+            if (t + 1) % every == 0:
+                w = ptsg.pt_measure(ref, what)
+                assert got[k * n_rec:(k + 1) * n_rec].tobytes() == w.tobytes(), (call, t)
+                k += 1
+        _same(_state(run, [L], [T], R), _state(ref, [L], [T], R), f"call {call}")
+    ptsg.pt_free(run)
+    ptsg.pt_free(ref)
+
+
 def test_run_argument_checks():
     import torch
     seed = 6200
