@@ -163,6 +163,23 @@ def mixed_cpu_baseline(Ls, cpl, temps, R, seed, n_hb, n_or, or_l):
     }
 
 
+def copy_rate(torch, mib, iters):
+    """GB/s (read + write bytes) of a torch device copy of `mib` MiB."""
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * (mib << 20) * iters / dt / 1e9, 1)
+
+
 def run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every, steps, warmup, timing=True,
         what=None):
     """Time `steps` steps after `warmup`; optionally a second pass with
@@ -286,6 +303,9 @@ def main():
     b = torch.empty_like(a)
     b.copy_(a)
     del a, b
+    # what plain streaming copies reach on this GPU, beside the spec peak:
+    # from HBM (1 GiB each way) and inside the Infinity Cache (64 MiB)
+    copy_rates = {"hbm_1GiB": copy_rate(torch, 1024, 20), "infinity_cache_64MiB": copy_rate(torch, 64, 200)}
 
     wall, su_per_step, kt, maps = run(ptsg, torch, Ls, cpl, temps, R, seed, flags, n_hb, n_or, every,
                                       args.steps, args.warmup, what=what)
@@ -343,6 +363,9 @@ def main():
         roof = None
     if roof is not None:
         roof["kernel_source_sha256"] = kernel_hash()
+        if roof["unit"] == "GB/s":
+            roof["measured_copy_GBps"] = copy_rates
+            roof["frac_of_hbm_copy"] = round(roof["achieved"] / copy_rates["hbm_1GiB"], 4)
 
     result = {
         "metric": METRIC,
