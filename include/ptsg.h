@@ -6,7 +6,8 @@
  * One Monte Carlo step of the paper (Sec. III and appendix A.1) is
  *     pt_step(ctx, 1, L);   pt_swap(ctx);
  * i.e. one heat-bath sweep, L overrelaxation sweeps, one parallel-tempering
- * pass.  Measurements (Sec. II.B) are taken with pt_measure.
+ * pass.  Measurements (Sec. II.B) are taken with pt_measure; pt_run runs many
+ * such steps, with a measurement every few, as replayed graphs.
  *
  * Model (Sec. II.A, Eq. (1)).  N = L^3 unit 3-vectors on a periodic cubic
  * lattice, site i = x + L*(y + L*z).  Each of the 3N bonds (i, i+e_mu),
@@ -37,9 +38,9 @@
  * Memory and streams.  Host arrays passed in are copied before the call
  * returns.  Device memory is either one caller-owned workspace (see
  * pt_workspace_size) or allocated by the library and released by pt_free.
- * Work is queued on the context's stream (pt_set_stream); pt_step and
- * pt_swap are asynchronous, every call that returns data to the host
- * synchronises the stream.  A context is not thread-safe; distinct contexts
+ * Work is queued on the context's stream (pt_set_stream); pt_step, pt_swap,
+ * pt_run and pt_measure_noalloc are asynchronous, every call that returns
+ * data to the host synchronises the stream.  A context is not thread-safe; distinct contexts
  * are independent.
  *
  * Errors.  Every call returns a pt_status; no C++ exception crosses the ABI.
