@@ -110,6 +110,21 @@ int main(void)
     CHECK(pt_get_spins(copy, 0, 1, 2, s2));
     for (int i = 0; i < 3 * N; ++i)
         if (s[i] != s2[i]) { fprintf(stderr, "resumed run differs at %d\n", i); return 1; }
+    /* three whole steps through pt_run on one, the separate calls on the
+       other: same spins and counters */
+    CHECK(pt_run(ctx, 3, 1, 2, 0, 0, NULL, 0));
+    for (int t = 0; t < 3; ++t) {
+        CHECK(pt_step(copy, 1, 2));
+        CHECK(pt_swap(copy));
+    }
+    CHECK(pt_get_spins(ctx, 0, 1, 2, s));
+    CHECK(pt_get_spins(copy, 0, 1, 2, s2));
+    for (int i = 0; i < 3 * N; ++i)
+        if (s[i] != s2[i]) { fprintf(stderr, "pt_run differs at %d\n", i); return 1; }
+    uint64_t hb1, pt1, hb2, pt2;
+    CHECK(pt_get_counters(ctx, &hb1, &pt1));
+    CHECK(pt_get_counters(copy, &hb2, &pt2));
+    if (hb1 != hb2 || pt1 != pt2) { fprintf(stderr, "pt_run counters differ\n"); return 1; }
     /* an invalid call reports through the status and the message */
     if (pt_step(ctx, -1, 0) != PT_EINVAL || pt_last_error()[0] == '\0') { fprintf(stderr, "error path\n"); return 1; }
     pt_free(copy);
