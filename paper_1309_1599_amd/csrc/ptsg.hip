@@ -1665,8 +1665,8 @@ pt_status pt_measure(pt_ctx *c, unsigned what, pt_meas *out, size_t cap, size_t 
 
 // pt_measure's records written to a device buffer, with the plane partials
 // in the fixed `scratch` array (records in chunks that fit it) and
-// chain-lane samples read in place (no staging copy): nothing is allocated,
-// nothing is copied to the host, nothing waits.
+// chain-lane samples staged in the context's own workspace: nothing is
+// allocated, nothing is copied to the host, nothing waits.
 pt_status pt_measure_noalloc(pt_ctx *c, unsigned what, pt_meas *d_out, size_t cap)
 {
     pt_status st = check_ctx(c);
