@@ -211,10 +211,15 @@ __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
     block_store<19>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kOverlapQ);
 }
 
-__global__ void finalize_kernel(MeasParams P)
+// One wave per record: lane q adds plane quantity q over z in order (and,
+// for Q(0) and kappa(0), its z Fourier pair with the twiddles), then writes
+// the record field(s) that quantity becomes; lane 0 writes the header.
+__global__ __launch_bounds__(kPlaneQ) void finalize_kernel(MeasParams P)
 {
-    const int rec = P.rec0 + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+    static_assert(kPlaneQ == 64, "one lane per plane quantity");
+    const int rec = P.rec0 + static_cast<int>(blockIdx.x);
     if (rec >= P.n_records) return;
+    const int q = static_cast<int>(threadIdx.x);
     const int *rd = P.rec + 4 * rec;
     const int s = rd[0], k = rd[1], ra = rd[2], rb = rd[3];
     const int L = P.L[s], T = P.n_temps[s];
@@ -224,53 +229,50 @@ __global__ void finalize_kernel(MeasParams P)
     pt_meas *out = P.cursor ? static_cast<pt_meas *>(P.cursor->base) + P.cursor->k * P.cursor->stride
                             : static_cast<pt_meas *>(P.out);
     pt_meas &m = out[rec];
-    m.sample = s;
-    m.tslot = k;
-    m.rep_a = ra;
-    m.rep_b = rb;
-    m.beta = P.betas[P.beta_base[s] + k];
-    const int *perm = P.perm + P.perm_base[s];
-    m.E_a = P.E[P.chain_base[s] + ra * T + perm[ra * T + k]];
-    m.E_b = P.E[P.chain_base[s] + rb * T + perm[rb * T + k]];
-    double sums[kPlaneQ], zr[9], zi[9], kzr[3], kzi[3];
-    for (int q = 0; q < kPlaneQ; ++q) sums[q] = 0.0;
-    for (int n = 0; n < 9; ++n) zr[n] = zi[n] = 0.0;
-    for (int n = 0; n < 3; ++n) kzr[n] = kzi[n] = 0.0;
+    if (q == 0) {
+        m.sample = s;
+        m.tslot = k;
+        m.rep_a = ra;
+        m.rep_b = rb;
+        m.beta = P.betas[P.beta_base[s] + k];
+        const int *perm = P.perm + P.perm_base[s];
+        m.E_a = P.E[P.chain_base[s] + ra * T + perm[ra * T + k]];
+        m.E_b = P.E[P.chain_base[s] + rb * T + perm[rb * T + k]];
+    }
+    double sum = 0.0, re = 0.0, im = 0.0;
     for (int z = 0; z < L; ++z) {
-        const double *pz = part + static_cast<int64_t>(z) * kPlaneQ;
-        for (int q = 0; q < kPlaneQ; ++q) sums[q] += pz[q];
-        for (int n = 0; n < 9; ++n) {
-            zr[n] += pz[kS0 + n] * cw[z];
-            zi[n] += pz[kS0 + n] * sw[z];
-        }
-        for (int n = 0; n < 3; ++n) {
-            kzr[n] += pz[kK0 + n] * cw[z];
-            kzi[n] += pz[kK0 + n] * sw[z];
-        }
+        const double v = part[static_cast<int64_t>(z) * kPlaneQ + q];
+        sum += v;
+        re += v * cw[z];
+        im += v * sw[z];
     }
     const bool ovl = P.what & PT_M_OVERLAP, chi = P.what & PT_M_CHIRAL, sd = P.what & PT_M_SD;
-    for (int n = 0; n < 9; ++n) {
-        m.q0[n] = ovl ? sums[kS0 + n] * invN : 0.0;
-        m.qk_re[0][n] = ovl ? sums[kSxR + n] * invN : 0.0;
-        m.qk_im[0][n] = ovl ? sums[kSxI + n] * invN : 0.0;
-        m.qk_re[1][n] = ovl ? sums[kSyR + n] * invN : 0.0;
-        m.qk_im[1][n] = ovl ? sums[kSyI + n] * invN : 0.0;
-        m.qk_re[2][n] = ovl ? zr[n] * invN : 0.0;
-        m.qk_im[2][n] = ovl ? zi[n] * invN : 0.0;
+    if (q < kK0) {
+        const int blk = q / 9, n = q - 9 * blk;      // Q(0), Q(kx) re, im, Q(ky) re, im
+        const double v = ovl ? sum * invN : 0.0;
+        if (blk == 0) {
+            m.q0[n] = v;
+            m.qk_re[2][n] = ovl ? re * invN : 0.0;   // k along z from the z planes
+            m.qk_im[2][n] = ovl ? im * invN : 0.0;
+        } else {
+            double *dst = (blk & 1) ? m.qk_re[(blk - 1) / 2] : m.qk_im[(blk - 1) / 2];
+            dst[n] = v;
+        }
+    } else if (q < kSD) {
+        const int blk = (q - kK0) / 3, n = q - kK0 - 3 * blk;   // kappa(0), kappa(kx) re, im, ...
+        const double v = chi ? sum * invN : 0.0;
+        if (blk == 0) {
+            m.cg0[n] = v;
+            m.cgk_re[2][n] = chi ? re * invN : 0.0;
+            m.cgk_im[2][n] = chi ? im * invN : 0.0;
+        } else {
+            double *dst = (blk & 1) ? m.cgk_re[(blk - 1) / 2] : m.cgk_im[(blk - 1) / 2];
+            dst[n] = v;
+        }
+    } else {
+        double *dst = q == kSD ? &m.sd1_a : q == kSD + 1 ? &m.sd2_a : q == kSD + 2 ? &m.sd1_b : &m.sd2_b;
+        *dst = sd ? sum : 0.0;
     }
-    for (int n = 0; n < 3; ++n) {
-        m.cg0[n] = chi ? sums[kK0 + n] * invN : 0.0;
-        m.cgk_re[0][n] = chi ? sums[kKxR + n] * invN : 0.0;
-        m.cgk_im[0][n] = chi ? sums[kKxI + n] * invN : 0.0;
-        m.cgk_re[1][n] = chi ? sums[kKyR + n] * invN : 0.0;
-        m.cgk_im[1][n] = chi ? sums[kKyI + n] * invN : 0.0;
-        m.cgk_re[2][n] = chi ? kzr[n] * invN : 0.0;
-        m.cgk_im[2][n] = chi ? kzi[n] * invN : 0.0;
-    }
-    m.sd1_a = sd ? sums[kSD + 0] : 0.0;
-    m.sd2_a = sd ? sums[kSD + 1] : 0.0;
-    m.sd1_b = sd ? sums[kSD + 2] : 0.0;
-    m.sd2_b = sd ? sums[kSD + 3] : 0.0;
 }
 
 }  // namespace
@@ -343,7 +345,7 @@ hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st)
 {
     const int n = p.n_records - p.rec0;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finalize_kernel, dim3((n + 63) / 64), dim3(64), 0, st, p);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n), dim3(kPlaneQ), 0, st, p);
     return hipGetLastError();
 }
 

@@ -25,23 +25,34 @@ __global__ void swap_kernel(SwapParams P)
     const int cb = P.chain_base[s] + r * T;
     const double *E = P.E + cb;
     const uint32_t pass = P.counters[1];
+    // The configuration that moves up the ladder is carried in registers
+    // (its chain a and energy ea): slot k + 1 still holds its value from
+    // before the pass when pair (k, k+1) is decided, and slot k is final
+    // once it is, so every load is independent of the decisions and each
+    // slot is written once.
+    int a = perm[0];
+    double ea = E[a];
     for (int k = 0; k + 1 < T; ++k) {
-        const int a = perm[k], b = perm[k + 1];
-        const double delta = (beta[k] - beta[k + 1]) * (E[a] - E[b]);
+        const int b = perm[k + 1];
+        const double eb = E[b];
+        const double delta = (beta[k] - beta[k + 1]) * (ea - eb);
         const uint4 w = philox10(make_uint4(static_cast<uint32_t>(k), pass,
                                             static_cast<uint32_t>(s),
                                             ctr_word3(1u, 0u, static_cast<uint32_t>(r))),
                                  P.key0, P.key1);
-        if (delta >= 0.0 || unit52(w.x, w.y) < exp(delta)) {
-            perm[k] = b;
-            perm[k + 1] = a;
+        const bool swap = delta >= 0.0 || unit52(w.x, w.y) < exp(delta);
+        const int stay = swap ? b : a;   // the configuration left at slot k
+        perm[k] = stay;
+        P.slot_of[cb + stay] = k;
+        P.beta_of[cb + stay] = static_cast<float>(beta[k]);
+        if (!swap) {
+            a = b;
+            ea = eb;
         }
     }
-    for (int k = 0; k < T; ++k) {
-        const int chain = cb + perm[k];
-        P.slot_of[chain] = k;
-        P.beta_of[chain] = static_cast<float>(beta[k]);
-    }
+    perm[T - 1] = a;
+    P.slot_of[cb + a] = T - 1;
+    P.beta_of[cb + a] = static_cast<float>(beta[T - 1]);
 }
 
 }  // namespace
