@@ -6,8 +6,9 @@
 // of k along z is constant on a plane).  FP32 x FP32 products are exact in
 // FP64.  Lane sums are reduced by wave shuffles and then across the four
 // waves in a fixed order, so results are bit-reproducible.
-// Stage 2: one lane per record adds the planes in order, applies the
-// z twiddles and the 1/N normalisation, and writes the record.
+// Stage 2: one wave per record, lane q adding plane quantity q over the
+// planes in order, applies the z twiddles and the 1/N normalisation, and
+// writes the record.
 #include "../../include/ptsg.h"
 #include "kernels.hpp"
 
@@ -124,14 +125,14 @@ __global__ __launch_bounds__(kMeasBlock) void overlap_plane_kernel(MeasParams P)
     block_store<45>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ);
 }
 
-__device__ __forceinline__ double chirality(const Chain &c, int x, int y, int z, int mu)
+// u is the chain's spin at (x, y, z), read once for the three directions.
+__device__ __forceinline__ double chirality(const Chain &c, const double (&u)[3], int x, int y, int z, int mu)
 {
     const int L = c.L;
     int p[3] = {x, y, z}, m[3] = {x, y, z};
     p[mu] = (p[mu] + 1 == L) ? 0 : p[mu] + 1;
     m[mu] = (m[mu] == 0) ? L - 1 : m[mu] - 1;
-    double u[3], v[3], w[3];
-    c.get(x, y, z, u);
+    double v[3], w[3];
     c.get(p[0], p[1], p[2], v);
     c.get(m[0], m[1], m[2], w);
     // zeta = s_{x+e} . (s_x cross s_{x-e})
@@ -169,46 +170,60 @@ __device__ __forceinline__ void field64(const Chain &c, const float *cpls, int x
     }
 }
 
+// Chiral-glass plane sums (slots kK0 .. kSD-1).
 __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
 {
     const int rec = P.rec0 + blockIdx.x, z = blockIdx.y;
     const RecordChains rc = record_chains(P, rec);
     const int L = rc.L;
     if (z >= L) return;
-    const bool chi = P.what & PT_M_CHIRAL, sd = P.what & PT_M_SD;
-    const float *cpl = P.cpls + P.cpls_base[rc.s];
-    double acc[19];
+    double acc[15];
 #pragma unroll
-    for (int q = 0; q < 19; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 15; ++q) acc[q] = 0.0;
     for (int idx = threadIdx.x; idx < L * L; idx += kMeasBlock) {
         const int x = idx % L, y = idx / L;
-        if (chi) {
-            const double cx = rc.cw[x], sx = rc.sw[x], cy = rc.cw[y], sy = rc.sw[y];
+        const double cx = rc.cw[x], sx = rc.sw[x], cy = rc.cw[y], sy = rc.sw[y];
+        double ua[3], ub[3];
+        rc.a.get(x, y, z, ua);
+        rc.b.get(x, y, z, ub);
 #pragma unroll
-            for (int mu = 0; mu < 3; ++mu) {
-                const double kap = chirality(rc.a, x, y, z, mu) * chirality(rc.b, x, y, z, mu);
-                acc[mu] += kap;
-                acc[3 + mu] += kap * cx;
-                acc[6 + mu] += kap * sx;
-                acc[9 + mu] += kap * cy;
-                acc[12 + mu] += kap * sy;
-            }
-        }
-        if (sd) {
-            double h[3], v[3];
-            field64(rc.a, cpl, x, y, z, h);
-            rc.a.get(x, y, z, v);
-            double sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
-            acc[15] += sh;
-            acc[16] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
-            field64(rc.b, cpl, x, y, z, h);
-            rc.b.get(x, y, z, v);
-            sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
-            acc[17] += sh;
-            acc[18] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
+        for (int mu = 0; mu < 3; ++mu) {
+            const double kap = chirality(rc.a, ua, x, y, z, mu) * chirality(rc.b, ub, x, y, z, mu);
+            acc[mu] += kap;
+            acc[3 + mu] += kap * cx;
+            acc[6 + mu] += kap * sx;
+            acc[9 + mu] += kap * cy;
+            acc[12 + mu] += kap * sy;
         }
     }
-    block_store<19>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kOverlapQ);
+    block_store<15>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kK0);
+}
+
+// Schwinger-Dyson plane sums (slots kSD .. kSD+3): s.h and |h|^2 - (s.h)^2
+// of both chains with the FP64 field.
+__global__ __launch_bounds__(kMeasBlock) void sd_plane_kernel(MeasParams P)
+{
+    const int rec = P.rec0 + blockIdx.x, z = blockIdx.y;
+    const RecordChains rc = record_chains(P, rec);
+    const int L = rc.L;
+    if (z >= L) return;
+    const float *cpl = P.cpls + P.cpls_base[rc.s];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int idx = threadIdx.x; idx < L * L; idx += kMeasBlock) {
+        const int x = idx % L, y = idx / L;
+        double h[3], v[3];
+        field64(rc.a, cpl, x, y, z, h);
+        rc.a.get(x, y, z, v);
+        double sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+        acc[0] += sh;
+        acc[1] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
+        field64(rc.b, cpl, x, y, z, h);
+        rc.b.get(x, y, z, v);
+        sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+        acc[2] += sh;
+        acc[3] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
+    }
+    block_store<4>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kSD);
 }
 
 // One wave per record: lane q adds plane quantity q over z in order (and,
@@ -289,11 +304,14 @@ __global__ __launch_bounds__(256) void cl_to_sl_kernel(const float *spins, int64
     const int p0 = blockIdx.x * 64, c = blockIdx.y, g = blockIdx.z;
     const int lane = threadIdx.x & 63;
     const float *src = spins + base + (static_cast<int64_t>(g) * 2 + c) * H * 192;
+    // 48 rows per wave, 16 loads in flight at a time
+#pragma unroll 16
     for (int row = threadIdx.x >> 6; row < 192; row += 4) {
         const int q = row / 3, k = row - 3 * q;
         if (p0 + q < H) tile[k][lane][q] = src[(static_cast<int64_t>(p0 + q) * 3 + k) * 64 + lane];
     }
     __syncthreads();
+#pragma unroll 16
     for (int row = threadIdx.x >> 6; row < 192; row += 4) {
         const int l = row / 3, k = row - 3 * l;
         const int j = g * 64 + l;
@@ -336,8 +354,10 @@ hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t
     const dim3 grid(n, L);
     if (p.what & PT_M_OVERLAP)
         hipLaunchKernelGGL(overlap_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
-    if (p.what & (PT_M_CHIRAL | PT_M_SD))
+    if (p.what & PT_M_CHIRAL)
         hipLaunchKernelGGL(chiral_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+    if (p.what & PT_M_SD)
+        hipLaunchKernelGGL(sd_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
     return hipGetLastError();
 }
 
