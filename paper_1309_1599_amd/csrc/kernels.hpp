@@ -123,7 +123,7 @@ struct SwapParams {
     const double *betas;         // [sample][T] by slot
     const int *chain_base, *perm_base, *beta_base, *n_temps;
     int n_samples, R;
-    const uint32_t *counters;    // device [1]: PT passes done (the pass counter)
+    uint32_t *counters;          // device [1]: PT passes done (read, then advanced by the kernel)
     uint32_t key0, key1;
 };
 

@@ -1542,7 +1542,7 @@ pt_status pt_step(pt_ctx *c, int n_hb, int n_or)
     return PT_OK;
 }
 
-// Queue one tempering pass and the advance of the pass counter.
+// Queue one tempering pass (its kernel advances the pass counter).
 static pt_status queue_swap(pt_ctx *c)
 {
     SwapParams p{};
@@ -1560,8 +1560,7 @@ static pt_status queue_swap(pt_ctx *c)
     p.counters = c->counters;
     p.key0 = static_cast<uint32_t>(c->seed);
     p.key1 = static_cast<uint32_t>(c->seed >> 32);
-    PT_HIP(launch_swap(p, c->stream));
-    PT_HIP(launch_advance_counters(c->counters, 0u, 1u, c->stream));
+    PT_HIP(launch_swap(p, c->stream));   // also advances the pass counter
     return PT_OK;
 }
 

@@ -6,6 +6,8 @@
 // temperatures, so only the slot labels (perm, slot_of, beta_of) change and
 // no spin moves.  The pairs are visited in ascending order within a pass,
 // which makes the pass sequential per (sample, replica): one lane each.
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "philox.hpp"
 
@@ -13,10 +15,9 @@ namespace ptsg {
 
 namespace {
 
-__global__ void swap_kernel(SwapParams P)
+// The pass of ladder t = (sample, replica).
+__device__ void swap_ladder(const SwapParams &P, int t, uint32_t pass)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= P.n_samples * P.R) return;
     const int s = t / P.R;
     const int r = t - s * P.R;
     const int T = P.n_temps[s];
@@ -24,7 +25,6 @@ __global__ void swap_kernel(SwapParams P)
     const double *beta = P.betas + P.beta_base[s];
     const int cb = P.chain_base[s] + r * T;
     const double *E = P.E + cb;
-    const uint32_t pass = P.counters[1];
     // The configuration that moves up the ladder is carried in registers
     // (its chain a and energy ea): slot k + 1 still holds its value from
     // before the pass when pair (k, k+1) is decided, and slot k is final
@@ -55,12 +55,26 @@ __global__ void swap_kernel(SwapParams P)
     P.beta_of[cb + a] = static_cast<float>(beta[T - 1]);
 }
 
+// One workgroup: thread t takes ladders t, t + blockDim.x, ...; after the
+// barrier, when every thread has read the pass counter, thread 0 advances
+// it (no separate launch for the counter).
+__global__ __launch_bounds__(1024) void swap_kernel(SwapParams P)
+{
+    const uint32_t pass = P.counters[1];
+    const int n = P.n_samples * P.R;
+    for (int t = static_cast<int>(threadIdx.x); t < n; t += static_cast<int>(blockDim.x))
+        swap_ladder(P, t, pass);
+    __syncthreads();
+    if (threadIdx.x == 0) P.counters[1] = pass + 1u;
+}
+
 }  // namespace
 
 hipError_t launch_swap(const SwapParams &p, hipStream_t st)
 {
     const int n = p.n_samples * p.R;
-    hipLaunchKernelGGL(swap_kernel, dim3((n + 63) / 64), dim3(64), 0, st, p);
+    const int block = std::min(1024, std::max(64, (n + 63) / 64 * 64));
+    hipLaunchKernelGGL(swap_kernel, dim3(1), dim3(block), 0, st, p);
     return hipGetLastError();
 }
 
