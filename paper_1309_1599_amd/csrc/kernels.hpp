@@ -243,7 +243,7 @@ hipError_t launch_chain_io(float *spins, int64_t base, int lanes, int L, int j, 
 // Plane kernels for records [rec0, rec0 + n) (lattices up to L), then, once
 // all records are done, the per-record finalisation of records
 // [rec0, n_records).
-hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st);
+hipError_t launch_measure_records(const MeasParams &p, int n, int L, int R, hipStream_t st);
 hipError_t launch_measure_finalize(const MeasParams &p, hipStream_t st);
 // One lane: cursor = {base, 0, stride}; cursor->k += 1.
 hipError_t launch_set_cursor(RecordCursor *cursor, void *base, uint64_t stride, hipStream_t st);

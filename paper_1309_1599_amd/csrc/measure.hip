@@ -199,6 +199,77 @@ __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
     block_store<15>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kK0);
 }
 
+// The chirality sums of all R(R-1)/2 records of one temperature slot (one
+// sample, replicas a < b in record order) in one workgroup: each chain's
+// chirality at a site is computed once for the slot instead of once per
+// record it belongs to.  Every record's sums are formed exactly as in
+// chiral_plane_kernel (same products, same order over the sites, same
+// reduction), so the results are bit-identical to it.
+template <int R>
+__global__ __launch_bounds__(kMeasBlock) void chiral_slot_kernel(MeasParams P)
+{
+    constexpr int NP = R * (R - 1) / 2, NQ = 15 * NP;
+    const int rec_first = P.rec0 + static_cast<int>(blockIdx.x) * NP, z = blockIdx.y;
+    const int *rd = P.rec + 4 * rec_first;
+    const int s = rd[0], k = rd[1];
+    const int L = P.L[s], T = P.n_temps[s];
+    if (z >= L) return;
+    const int H = L * L * L / 2;
+    const int *perm = P.perm + P.perm_base[s];
+    const bool staged = s == P.stage_sample;
+    const float *src = staged ? P.stage : P.spins;
+    const int64_t base = staged ? 0 : P.spin_base[s];
+    const int lanes = staged ? 1 : P.lanes[s];
+    Chain ch[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ch[r] = Chain{src, base, lanes, r * T + perm[r * T + k], L, L / 2, H};
+    const double *cw = P.twid + P.twid_base[s], *sw = cw + L;
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int idx = threadIdx.x; idx < L * L; idx += kMeasBlock) {
+        const int x = idx % L, y = idx / L;
+        const double cx = cw[x], sx = sw[x], cy = cw[y], sy = sw[y];
+        double zeta[R][3];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double u[3];
+            ch[r].get(x, y, z, u);
+#pragma unroll
+            for (int mu = 0; mu < 3; ++mu) zeta[r][mu] = chirality(ch[r], u, x, y, z, mu);
+        }
+        int p = 0;
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = a + 1; b < R; ++b, ++p)
+#pragma unroll
+                for (int mu = 0; mu < 3; ++mu) {
+                    const double kap = zeta[a][mu] * zeta[b][mu];
+                    double *q = acc + 15 * p;
+                    q[mu] += kap;
+                    q[3 + mu] += kap * cx;
+                    q[6 + mu] += kap * sx;
+                    q[9 + mu] += kap * cy;
+                    q[12 + mu] += kap * sy;
+                }
+    }
+    __shared__ double red[kMeasBlock / 64][NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < NQ; q += kMeasBlock) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kMeasBlock / 64; ++w) v += red[w][q];
+        const int rec = rec_first + q / 15;
+        P.part[(static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kK0 + q % 15] = v;
+    }
+}
+
 // Schwinger-Dyson plane sums (slots kSD .. kSD+3): s.h and |h|^2 - (s.h)^2
 // of both chains with the FP64 field.
 __global__ __launch_bounds__(kMeasBlock) void sd_plane_kernel(MeasParams P)
@@ -348,14 +419,24 @@ hipError_t launch_advance_cursor(RecordCursor *cursor, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_measure_records(const MeasParams &p, int n, int L, hipStream_t st)
+hipError_t launch_measure_records(const MeasParams &p, int n, int L, int R, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
     const dim3 grid(n, L);
     if (p.what & PT_M_OVERLAP)
         hipLaunchKernelGGL(overlap_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
-    if (p.what & PT_M_CHIRAL)
-        hipLaunchKernelGGL(chiral_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+    if (p.what & PT_M_CHIRAL) {
+        // whole slots (R = 3 or 4 and a range of whole slots): one workgroup per
+        // slot and plane; otherwise one per record and plane (same results)
+        const int np = R * (R - 1) / 2;
+        if ((R == 3 || R == 4) && n % np == 0) {
+            const dim3 g(n / np, L);
+            if (R == 3) hipLaunchKernelGGL(chiral_slot_kernel<3>, g, dim3(kMeasBlock), 0, st, p);
+            else hipLaunchKernelGGL(chiral_slot_kernel<4>, g, dim3(kMeasBlock), 0, st, p);
+        } else {
+            hipLaunchKernelGGL(chiral_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+        }
+    }
     if (p.what & PT_M_SD)
         hipLaunchKernelGGL(sd_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
     return hipGetLastError();

@@ -1613,7 +1613,7 @@ static pt_status queue_measure(pt_ctx *c, unsigned what, bool to_cursor = false)
             if (end <= run_start) return hipSuccess;
             MeasParams q = m;
             q.rec0 = run_start;
-            return launch_measure_records(q, end - run_start, run_L, c->stream);
+            return launch_measure_records(q, end - run_start, run_L, P.R, c->stream);
         };
         for (int s = 0; s < P.S; ++s) {
             const int n = P.T[s] * P.R * (P.R - 1) / 2;
@@ -1625,7 +1625,7 @@ static pt_status queue_measure(pt_ctx *c, unsigned what, bool to_cursor = false)
                 MeasParams q = m;
                 q.stage_sample = s;
                 q.rec0 = first;
-                PT_HIP(launch_measure_records(q, n, L, c->stream));
+                PT_HIP(launch_measure_records(q, n, L, P.R, c->stream));
                 run_start = first + n;
                 run_L = 0;
             } else {
@@ -1686,7 +1686,11 @@ pt_status pt_measure_noalloc(pt_ctx *c, unsigned what, pt_meas *d_out, size_t ca
                                          std::to_string(kScratchDoubles * 8) + " bytes");
     double *part = nullptr;
     if ((st = scratch_on(c->device, &part)) != PT_OK) return st;
-    const int chunk = static_cast<int>(std::min<size_t>(kScratchDoubles / per_record, P.n_records));
+    // whole temperature slots per chunk (the R(R-1)/2 records of a slot are
+    // measured together), as many as the scratch array holds
+    const int np = P.R * (P.R - 1) / 2;
+    int chunk = static_cast<int>(std::min<size_t>(kScratchDoubles / per_record, P.n_records));
+    if (chunk >= np) chunk -= chunk % np;
     MeasParams m{};
     m.spins = c->spins;
     m.cpls = c->cpls;
@@ -1719,7 +1723,7 @@ pt_status pt_measure_noalloc(pt_ctx *c, unsigned what, pt_meas *d_out, size_t ca
             q.rec0 = r0;
             q.part_rec0 = r0;
             q.n_records = std::min(r0 + chunk, b);
-            hipError_t e = launch_measure_records(q, q.n_records - r0, L, c->stream);
+            hipError_t e = launch_measure_records(q, q.n_records - r0, L, P.R, c->stream);
             if (e == hipSuccess) e = launch_measure_finalize(q, c->stream);
             if (e != hipSuccess) return e;
         }

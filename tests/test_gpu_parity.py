@@ -180,7 +180,7 @@ def _oracle_record(L, M, sa, sb):
 
 
 @pytest.mark.parametrize("mapping", MAPPINGS)
-@pytest.mark.parametrize("Ls,R", [([8], 2), ([6, 10], 3)])
+@pytest.mark.parametrize("Ls,R", [([8], 2), ([6, 10], 3), ([6, 8], 4)])
 def test_measure_parity(Ls, R, mapping):
     seed = 500
     temps = [inputs.geometric_temps(0.6, 1.6, 3) for _ in Ls]
