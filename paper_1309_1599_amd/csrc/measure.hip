@@ -5,7 +5,9 @@
 // the products f(x) and f(x) exp(i k x_d) for k along x and y (the twiddle
 // of k along z is constant on a plane).  FP32 x FP32 products are exact in
 // FP64.  Lane sums are reduced by wave shuffles and then across the four
-// waves in a fixed order, so results are bit-reproducible.
+// waves in a fixed order, so results are bit-reproducible.  (The chirality
+// sums of 3 or 4 replicas take one workgroup per (temperature slot, z
+// plane) for all the slot's records, with the same per-record arithmetic.)
 // Stage 2: one wave per record, lane q adding plane quantity q over the
 // planes in order, applies the z twiddles and the 1/N normalisation, and
 // writes the record.
