@@ -6,8 +6,9 @@
 // of k along z is constant on a plane).  FP32 x FP32 products are exact in
 // FP64.  Lane sums are reduced by wave shuffles and then across the four
 // waves in a fixed order, so results are bit-reproducible.  (The chirality
-// sums of 3 or 4 replicas take one workgroup per (temperature slot, z
-// plane) for all the slot's records, with the same per-record arithmetic.)
+// and Schwinger-Dyson sums of 3 or 4 replicas take one workgroup per
+// (temperature slot, z plane) for all the slot's records, with the same
+// per-record arithmetic.)
 // Stage 2: one wave per record, lane q adding plane quantity q over the
 // planes in order, applies the z twiddles and the 1/N normalisation, and
 // writes the record.
@@ -204,9 +205,9 @@ __global__ __launch_bounds__(kMeasBlock) void chiral_plane_kernel(MeasParams P)
 // The chirality sums of all R(R-1)/2 records of one temperature slot (one
 // sample, replicas a < b in record order) in one workgroup: each chain's
 // chirality at a site is computed once for the slot instead of once per
-// record it belongs to.  Every record's sums are formed exactly as in
-// chiral_plane_kernel (same products, same order over the sites, same
-// reduction), so the results are bit-identical to it.
+// record it belongs to.  Every record's sums are formed as in
+// chiral_plane_kernel: the same products, in the same order over the sites,
+// and the same reduction.
 template <int R>
 __global__ __launch_bounds__(kMeasBlock) void chiral_slot_kernel(MeasParams P)
 {
@@ -297,6 +298,74 @@ __global__ __launch_bounds__(kMeasBlock) void sd_plane_kernel(MeasParams P)
         acc[3] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
     }
     block_store<4>(acc, P.part + (static_cast<int64_t>(rec - P.part_rec0) * P.Lmax + z) * kPlaneQ + kSD);
+}
+
+// The Schwinger-Dyson sums of the R chains of one temperature slot, each
+// computed once and written into every record of the slot that holds the
+// chain (as chain a or b); per chain the sums are formed as in
+// sd_plane_kernel: the same terms, in the same order over the sites, and the
+// same reduction.
+template <int R>
+__global__ __launch_bounds__(kMeasBlock) void sd_slot_kernel(MeasParams P)
+{
+    constexpr int NP = R * (R - 1) / 2, NQ = 2 * R;
+    const int rec_first = P.rec0 + static_cast<int>(blockIdx.x) * NP, z = blockIdx.y;
+    const int *rd = P.rec + 4 * rec_first;
+    const int s = rd[0], k = rd[1];
+    const int L = P.L[s], T = P.n_temps[s];
+    if (z >= L) return;
+    const int H = L * L * L / 2;
+    const int *perm = P.perm + P.perm_base[s];
+    const bool staged = s == P.stage_sample;
+    const float *src = staged ? P.stage : P.spins;
+    const int64_t base = staged ? 0 : P.spin_base[s];
+    const int lanes = staged ? 1 : P.lanes[s];
+    const float *cpl = P.cpls + P.cpls_base[s];
+    double acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int idx = threadIdx.x; idx < L * L; idx += kMeasBlock) {
+        const int x = idx % L, y = idx / L;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const Chain c{src, base, lanes, r * T + perm[r * T + k], L, L / 2, H};
+            double h[3], v[3];
+            field64(c, cpl, x, y, z, h);
+            c.get(x, y, z, v);
+            const double sh = v[0] * h[0] + v[1] * h[1] + v[2] * h[2];
+            acc[2 * r] += sh;
+            acc[2 * r + 1] += h[0] * h[0] + h[1] * h[1] + h[2] * h[2] - sh * sh;
+        }
+    }
+    __shared__ double red[kMeasBlock / 64][NQ];
+    __shared__ double chain_sum[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double v = wave_sum(acc[q]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kMeasBlock / 64; ++w) v += red[w][threadIdx.x];
+        chain_sum[threadIdx.x] = v;
+    }
+    __syncthreads();
+    // record p = (a, b) gets sd1_a sd2_a sd1_b sd2_b
+    if (threadIdx.x < 4 * NP) {
+        const int p = threadIdx.x / 4, f = threadIdx.x % 4;
+        int a = 0, b = 1, i = 0;
+        for (int aa = 0; aa < R; ++aa)
+            for (int bb = aa + 1; bb < R; ++bb, ++i)
+                if (i == p) {
+                    a = aa;
+                    b = bb;
+                }
+        const int r = f < 2 ? a : b;
+        P.part[(static_cast<int64_t>(rec_first + p - P.part_rec0) * P.Lmax + z) * kPlaneQ + kSD + f] =
+            chain_sum[2 * r + (f & 1)];
+    }
 }
 
 // One wave per record: lane q adds plane quantity q over z in order (and,
@@ -429,7 +498,7 @@ hipError_t launch_measure_records(const MeasParams &p, int n, int L, int R, hipS
         hipLaunchKernelGGL(overlap_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
     if (p.what & PT_M_CHIRAL) {
         // whole slots (R = 3 or 4 and a range of whole slots): one workgroup per
-        // slot and plane; otherwise one per record and plane (same results)
+        // slot and plane; otherwise one per record and plane (same arithmetic)
         const int np = R * (R - 1) / 2;
         if ((R == 3 || R == 4) && n % np == 0) {
             const dim3 g(n / np, L);
@@ -439,8 +508,16 @@ hipError_t launch_measure_records(const MeasParams &p, int n, int L, int R, hipS
             hipLaunchKernelGGL(chiral_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
         }
     }
-    if (p.what & PT_M_SD)
-        hipLaunchKernelGGL(sd_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+    if (p.what & PT_M_SD) {
+        const int np = R * (R - 1) / 2;
+        if ((R == 3 || R == 4) && n % np == 0) {
+            const dim3 g(n / np, L);
+            if (R == 3) hipLaunchKernelGGL(sd_slot_kernel<3>, g, dim3(kMeasBlock), 0, st, p);
+            else hipLaunchKernelGGL(sd_slot_kernel<4>, g, dim3(kMeasBlock), 0, st, p);
+        } else {
+            hipLaunchKernelGGL(sd_plane_kernel, grid, dim3(kMeasBlock), 0, st, p);
+        }
+    }
     return hipGetLastError();
 }
 
