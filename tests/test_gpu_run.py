@@ -106,6 +106,33 @@ def test_run_many_short_steps(every):
     ptsg.pt_free(ref)
 
 
+def test_run_four_replicas_all_measurements():
+    """R = 4 (six records per temperature slot, the slot-wise chirality and
+    Schwinger-Dyson kernels) with every measurement bit, inside the replayed
+    graphs: records and state equal to the separate calls."""
+    import torch
+    seed = 6400
+    Ls, Ts, R = [8, 12], [4, 3], 4
+    temps = [inputs.geometric_temps(0.6, 1.6, T) for T in Ts]
+    cpl = [inputs.gaussian_couplings(L, seed, s) for s, L in enumerate(Ls)]
+    run = ptsg.pt_init_batch(Ls, cpl, temps, R, seed, flags=ptsg.PT_F_GRAPHS)
+    ref = ptsg.pt_init_batch(Ls, cpl, temps, R, seed)
+    n_rec = run.n_records
+    assert n_rec == 6 * sum(Ts)
+    buf = torch.zeros(5 * n_rec * ptsg.MEAS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    ptsg.pt_run(run, 5, 1, ptsg.PT_OR_L, 1, ptsg.PT_M_ALL, buf.data_ptr(), 5 * n_rec)
+    ptsg.pt_sync(run)
+    got = np.frombuffer(buf.cpu().numpy().tobytes(), dtype=ptsg.MEAS_DTYPE)
+    for t in range(5):
+        ptsg.pt_step(ref, 1, ptsg.PT_OR_L)
+        ptsg.pt_swap(ref)
+        w = ptsg.pt_measure(ref, ptsg.PT_M_ALL)
+        assert got[t * n_rec:(t + 1) * n_rec].tobytes() == w.tobytes(), t
+    _same(_state(run, Ls, Ts, R), _state(ref, Ls, Ts, R), "R = 4")
+    ptsg.pt_free(run)
+    ptsg.pt_free(ref)
+
+
 def test_run_argument_checks():
     import torch
     seed = 6200
