@@ -129,7 +129,15 @@ __device__ __forceinline__ void st(Rsrc r, float v, unsigned voff, unsigned soff
 // The grid has 8*per (kXcds*per) workgroups; those mapped beyond the last
 // tile exit.
 
-__device__ __forceinline__ int xcd_tile(int w, int per) { return (w % kXcds) * per + w / kXcds; }
+// With `reverse` each XCD takes its range backwards: the colour-1
+// half-sweeps do, so that a half-sweep begins where the one before it ended
+// (measured: chain lanes at L64x8 1 % faster, site lanes at L32x64 0.3 %;
+// the results do not change, since same-colour sites are independent).
+__device__ __forceinline__ int xcd_tile(int w, int per, bool reverse = false)
+{
+    const int i = w / kXcds;
+    return (w % kXcds) * per + (reverse ? per - 1 - i : i);
+}
 
 // h_a = sum over the six neighbours n (+x, -x, +y, -y, +z, -z) and b of
 // A_n[a][b] s_n[b], accumulated in exactly this order (first term a product,

@@ -138,7 +138,7 @@ __device__ __forceinline__ void half_sweep_block(Params &P, unsigned bx, unsigne
 {
     constexpr bool kOwn = KIND != kHeatbath;  // heat-bath ignores the old spin
     const int s = P.samples[bz];
-    const int tile = xcd_tile(bx, P.per);
+    const int tile = xcd_tile(bx, P.per, P.colour == 1);   // colour 1 backwards
     if (tile >= P.n_tiles) return;
     const int p = tile * kSweepBlock + threadIdx.x;
     const bool active = p < P.H;

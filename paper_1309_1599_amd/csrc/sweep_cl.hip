@@ -119,7 +119,7 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
     }
 
     // This wave's segment: packed row `row` (= y + L*z), x-halves [x0, x0 + len).
-    const int tile = xcd_tile(bx, P.per);
+    const int tile = xcd_tile(bx, P.per, P.colour == 1);   // colour 1 backwards
     if (tile >= P.n_tiles) return;
     const int seg = tile * kClWaves + wave;
     const int rl = seg / P.split;                 // row in visiting order
