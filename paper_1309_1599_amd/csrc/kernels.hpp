@@ -91,6 +91,9 @@ struct ClParams {
     int L, H, C, T;
     int bimodal;                 // cpl holds bond codes; bm_table their matrices
     const float *bm_table;       // [sample][128][9]: the matrix of each code (bimodal samples)
+    int canon;                   // float couplings read from the canonical blocks below
+    const float *cpls;           // site-major canonical couplings [N][27] per sample
+    const int64_t *cpls_base;
     int split;                   // waves per packed row (divides L/2)
     int strip;                   // row order: strips of `strip` y-rows, z-major within a strip (0: y-major)
     int n_tiles, per;            // workgroups of rows per item; per XCD (grid = 8*per)

@@ -509,6 +509,9 @@ ClParams cl_params(pt_ctx *c, const LatticeClass &k, int first_item, int colour,
     p.T = k.T;
     p.bimodal = c->plan.codes[k.samples[0]];
     p.bm_table = c->bm_table;
+    p.canon = !p.bimodal;   // overrelaxation and energy half-sweeps read the canonical blocks
+    p.cpls = c->cpls;
+    p.cpls_base = c->d_cpls_base;
     p.split = k.split;
     p.strip = k.strip;
     p.n_tiles = k.blocks;

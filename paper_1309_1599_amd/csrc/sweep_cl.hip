@@ -39,10 +39,104 @@ using CFloat = __attribute__((address_space(4))) const float;
 
 constexpr unsigned kRow = 3u * 64u * 4u;  // bytes of one site of one group: 3 components x 64 lanes
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 struct ClGather {
     float o[3];
     float n[6][3];
+    v4f cv;   // canonical couplings: four coefficients of the site per lane (see canon_lane)
 };
+
+// Canonical-block couplings: in each 16-lane row, lanes 0-6 hold floats
+// 0..27 of the site's own block (its three forward matrices), lanes 7-9,
+// 10-12 and 13-15 floats of the x-, y- and z-bond matrix of the backward
+// neighbour along x, y and z (four floats a lane, 9 of 12 used).  Lane k
+// reads 16 bytes at float 27*site + off from the site of kind `kind`
+// (0 own, 1..3 backward along x, y, z).
+struct CanonLane {
+    int kind;
+    unsigned off;
+};
+
+__device__ __forceinline__ CanonLane canon_lane(int lane)
+{
+    const int k = lane & 15;
+    if (k < 7) return CanonLane{0, 4u * static_cast<unsigned>(k)};
+    const int mu = (k - 7) / 3, m = (k - 7) - 3 * mu;
+    return CanonLane{1 + mu, static_cast<unsigned>(9 * mu + 4 * m)};
+}
+
+// The local field of spin_update.hpp's local_field, term for term in the
+// same order per component, each coefficient taken by a DPP row broadcast
+// inside the multiply-add from the lane that holds it (the layout above:
+// A_{2mu}[a][b] is float 9mu + 3a + b of the own block, A_{2mu+1}[a][b]
+// float 3b + a of the mu-bond matrix of the backward neighbour).  The three
+// components are interleaved, so every instruction is at least two after
+// the one that wrote the accumulator it reads (the DPP read-after-write
+// distance); the leading s_nop covers VALU writes of the inputs before it.
+__device__ __forceinline__ void local_field_rows(const float (&sn)[6][3], const v4f &cv, float (&h)[3])
+{
+    asm("s_nop 4\n"
+        "v_mul_f32_dpp %0, %3, %7 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+        "v_mul_f32_dpp %1, %6, %7 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+        "v_mul_f32_dpp %2, %5, %7 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %4, %8 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %3, %8 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %6, %8 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %5, %9 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %4, %9 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %3, %9 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %3, %10 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %4, %10 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %5, %10 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %6, %11 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %3, %11 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %4, %11 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %5, %12 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %6, %12 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %3, %12 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %4, %13 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %3, %13 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %6, %13 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %5, %14 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %4, %14 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %3, %14 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %6, %15 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %5, %15 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %4, %15 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %3, %16 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %4, %16 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %5, %16 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %6, %17 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %3, %17 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %4, %17 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %5, %18 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %6, %18 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %3, %18 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %5, %19 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %4, %19 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %3, %19 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %6, %20 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %5, %20 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %4, %20 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %3, %21 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %6, %21 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %5, %21 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %3, %22 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %4, %22 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %5, %22 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %6, %23 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %3, %23 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %4, %23 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %0, %5, %24 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %1, %6, %24 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+        "v_fmac_f32_dpp %2, %3, %24 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+        : "=&v"(h[0]), "=&v"(h[1]), "=&v"(h[2])
+        : "v"(cv[0]), "v"(cv[1]), "v"(cv[2]), "v"(cv[3]),
+          "v"(sn[0][0]), "v"(sn[0][1]), "v"(sn[0][2]), "v"(sn[1][0]), "v"(sn[1][1]), "v"(sn[1][2]),
+          "v"(sn[2][0]), "v"(sn[2][1]), "v"(sn[2][2]), "v"(sn[3][0]), "v"(sn[3][1]), "v"(sn[3][2]),
+          "v"(sn[4][0]), "v"(sn[4][1]), "v"(sn[4][2]), "v"(sn[5][0]), "v"(sn[5][1]), "v"(sn[5][2]));
+}
 
 __device__ __forceinline__ void load_site(float (&v)[3], Rsrc r, unsigned voff, unsigned soff)
 {
@@ -59,10 +153,10 @@ struct ClSite {
     unsigned cpl;        // first of the site's 54 coupling floats
     uint32_t lo, hi;     // bond codes of A_0..A_3 and A_4, A_5 (bimodal samples)
     int site;            // canonical index
+    unsigned cvoff;      // canonical couplings: this lane's byte offset (canon_lane)
 };
 
 typedef float v16f __attribute__((ext_vector_type(16)));
-typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 using CV16 = __attribute__((address_space(4))) const v16f;
 using CV4 = __attribute__((address_space(4))) const v4f;
@@ -71,21 +165,25 @@ typedef float v8f __attribute__((ext_vector_type(8)));
 using CV8 = __attribute__((address_space(4))) const v8f;
 using CU32 = __attribute__((address_space(4))) const uint32_t;
 
-template <bool OWN>
-__device__ __forceinline__ void cl_gather(ClGather &g, Rsrc r, unsigned voff, const ClSite &t)
+template <bool OWN, bool CANON>
+__device__ __forceinline__ void cl_gather(ClGather &g, Rsrc r, unsigned voff, const ClSite &t, Rsrc rc)
 {
 #pragma unroll
     for (int n = 0; n < 6; ++n) load_site(g.n[n], r, voff, t.nb[n]);
     if constexpr (OWN) load_site(g.o, r, voff, t.own);
+    if constexpr (CANON)
+        g.cv = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rc, t.cvoff, 0, 0));
 }
 
 using ClEWave = double[kClWaves][64];
 
 // One workgroup's share of a half-sweep: block (bx, bz) of the launch grid
 // (8*per, 1, items).  `e_wave` is LDS for the energy partials (ENERGY only).
-template <int KIND, bool ENERGY, bool BM, class Params>
+template <int KIND, bool ENERGY, int CM, class Params>
 __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsigned bz, ClEWave *e_wave)
 {
+    constexpr bool BM = CM == 1;      // bond codes and the per-sample matrix table
+    constexpr bool CANON = CM == 2;   // float couplings from the canonical blocks
     constexpr bool kOwn = KIND != kHeatbath;
     const int s = P.items[2 * bz];
     const int g = P.items[2 * bz + 1];
@@ -108,6 +206,9 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
     // enough to stay in the scalar cache
     const CU32 *codes = (const CU32 *)(P.cpl + P.cpl_base[s]);
     const CFloat *table = BM ? (const CFloat *)(P.bm_table) + s * (128 * 9) : nullptr;
+    // canonical blocks of the sample (27 floats a site) and this lane's part
+    const Rsrc rc = make_rsrc(CANON ? P.cpls + P.cpls_base[s] : P.cpl, CANON ? 2u * H * 27u * 4u : 0u);
+    const CanonLane cl = canon_lane(lane);
 
     uint32_t ctr3 = 0, hb_sweep = 0;
     float beta = 0.0f;
@@ -164,6 +265,16 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
             t.nb[5] = b_zm + o;
             t.site = rowc + x;
             t.cpl = (c_site + static_cast<unsigned>(xh)) * 54u;
+            if constexpr (CANON) {
+                // canonical index of the site of this lane's kind: own, or the
+                // backward neighbour along x, y or z
+                const int xm = x == 0 ? L - 1 : x - 1;
+                const int sx = rowc + xm;
+                const int sy = (y == 0 ? t.site + (L - 1) * L : t.site - L);
+                const int sz = (z == 0 ? t.site + (L - 1) * L * L : t.site - L * L);
+                const int sel = cl.kind == 0 ? t.site : cl.kind == 1 ? sx : cl.kind == 2 ? sy : sz;
+                t.cvoff = (27u * static_cast<unsigned>(sel) + cl.off) * 4u;
+            }
             if constexpr (BM) {
                 t.lo = codes[2 * (c_site + static_cast<unsigned>(xh))];
                 t.hi = codes[2 * (c_site + static_cast<unsigned>(xh)) + 1];
@@ -194,6 +305,8 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
                     const int q = a * 3 + b;
                     return q < 8 ? m8[n][q] : m1[n];
                 }, h);
+            } else if constexpr (CANON) {
+                local_field_rows(gt.n, gt.cv, h);
             } else {
                 const CFloat *A = M + t.cpl;
                 const v16f a0 = *(CV16 *)(A);
@@ -231,18 +344,18 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
         // the current site is updated
         ClGather ga, gb;
         ClSite ta = site_at(x0), tb;
-        cl_gather<kOwn>(ga, r, voff, ta);
+        cl_gather<kOwn, CANON>(ga, r, voff, ta, rc);
         for (int xh = x0; xh < x0 + len; xh += 2) {
             const bool has_b = xh + 1 < x0 + len;
             if (has_b) {
                 tb = site_at(xh + 1);
-                cl_gather<kOwn>(gb, r, voff, tb);
+                cl_gather<kOwn, CANON>(gb, r, voff, tb, rc);
             }
             process(ga, ta);
             if (!has_b) break;
             if (xh + 2 < x0 + len) {
                 ta = site_at(xh + 2);
-                cl_gather<kOwn>(ga, r, voff, ta);
+                cl_gather<kOwn, CANON>(ga, r, voff, ta, rc);
             }
             process(gb, tb);
         }
@@ -261,14 +374,14 @@ __device__ __forceinline__ void cl_half_sweep_block(Params &P, unsigned bx, unsi
     }
 }
 
-template <int KIND, bool ENERGY, bool BM>
+template <int KIND, bool ENERGY, int CM>
 __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
 {
     if constexpr (ENERGY) {
         __shared__ ClEWave e_wave;
-        cl_half_sweep_block<KIND, ENERGY, BM>(P, blockIdx.x, blockIdx.z, &e_wave);
+        cl_half_sweep_block<KIND, ENERGY, CM>(P, blockIdx.x, blockIdx.z, &e_wave);
     } else {
-        cl_half_sweep_block<KIND, ENERGY, BM>(P, blockIdx.x, blockIdx.z, nullptr);
+        cl_half_sweep_block<KIND, ENERGY, CM>(P, blockIdx.x, blockIdx.z, nullptr);
     }
 }
 
@@ -276,7 +389,7 @@ __global__ __launch_bounds__(kClBlock) void cl_half_sweep_kernel(ClParams P)
 using CDesc = __attribute__((address_space(4))) const StepDesc;
 using CInt = __attribute__((address_space(4))) const int;
 
-template <bool BM, class Params>
+template <int BM, class Params>
 __device__ __forceinline__ void cl_dispatch(Params &p, int kind, int energy, unsigned bx, unsigned bz, ClEWave *ew)
 {
     if (kind == kOverrelax) {
@@ -345,16 +458,25 @@ hipError_t launch_cl_half_sweep(int kind, bool energy, const ClParams &p, int n_
     auto go = [&](auto kernel) { return launch_kernel(kernel, grid, block, 0, st, t, p); };
     if (p.bimodal) {
         if (kind == kOverrelax)
-            return energy ? go(cl_half_sweep_kernel<kOverrelax, true, true>) : go(cl_half_sweep_kernel<kOverrelax, false, true>);
+            return energy ? go(cl_half_sweep_kernel<kOverrelax, true, 1>) : go(cl_half_sweep_kernel<kOverrelax, false, 1>);
         if (kind == kHeatbath)
-            return energy ? go(cl_half_sweep_kernel<kHeatbath, true, true>) : go(cl_half_sweep_kernel<kHeatbath, false, true>);
-        return go(cl_half_sweep_kernel<kEnergyOnly, true, true>);
+            return energy ? go(cl_half_sweep_kernel<kHeatbath, true, 1>) : go(cl_half_sweep_kernel<kHeatbath, false, 1>);
+        return go(cl_half_sweep_kernel<kEnergyOnly, true, 1>);
     }
+    // Float couplings: the overrelaxation and energy half-sweeps read the
+    // canonical blocks (27 floats a site: a group and its sample's couplings
+    // then fit the Infinity Cache), the heat-bath ones the packed blocks (the
+    // canonical form's extra registers cost that VALU-bound kernel more
+    // than its bytes save).
+    if (p.canon && kind != kHeatbath)
+        return kind == kOverrelax
+                   ? (energy ? go(cl_half_sweep_kernel<kOverrelax, true, 2>) : go(cl_half_sweep_kernel<kOverrelax, false, 2>))
+                   : go(cl_half_sweep_kernel<kEnergyOnly, true, 2>);
     if (kind == kOverrelax)
-        return energy ? go(cl_half_sweep_kernel<kOverrelax, true, false>) : go(cl_half_sweep_kernel<kOverrelax, false, false>);
+        return energy ? go(cl_half_sweep_kernel<kOverrelax, true, 0>) : go(cl_half_sweep_kernel<kOverrelax, false, 0>);
     if (kind == kHeatbath)
-        return energy ? go(cl_half_sweep_kernel<kHeatbath, true, false>) : go(cl_half_sweep_kernel<kHeatbath, false, false>);
-    return go(cl_half_sweep_kernel<kEnergyOnly, true, false>);
+        return energy ? go(cl_half_sweep_kernel<kHeatbath, true, 0>) : go(cl_half_sweep_kernel<kHeatbath, false, 0>);
+    return go(cl_half_sweep_kernel<kEnergyOnly, true, 0>);
 }
 
 }  // namespace ptsg
