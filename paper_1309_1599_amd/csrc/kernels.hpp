@@ -18,8 +18,9 @@
 //          lanes = 64, stores group g = j/64 of a sample as
 //          [colour][H][component][64], lane = j%64; see spin_index.)
 //          Chain-lane samples keep the same 54 numbers per site site-major,
-//          [colour 2][H][54]: one 216-byte block per site, which a wave
-//          reads with five back-to-back scalar loads.
+//          [colour 2][H][54]: one 216-byte block per site, which a
+//          heat-bath wave reads with five back-to-back scalar loads (the
+//          overrelaxation and energy waves read the canonical blocks).
 //  cpls    per sample, site-major canonical couplings [N][3][3][3]: the
 //          three forward bond matrices of site i are floats 27i .. 27i+26.
 //  chains  global chain id = chain_base[sample] + rep*T + j, j = start slot.

@@ -2,10 +2,14 @@
 //
 // One wave = 64 chains of one sample at the same site: lane l owns chain
 // 64*g + l of chain group g.  All lanes read the same site, so
-//  * the site's six matrices are wave-uniform: they sit in one 216-byte
-//    block of the per-site packed couplings [colour][H][54], which five
-//    scalar loads issued back to back bring into SGPRs (one memory round
-//    trip per site, no vector registers);
+//  * the site's six matrices are wave-uniform.  The overrelaxation and
+//    energy half-sweeps read them from the canonical 27-float blocks (the
+//    site's own block and the backward neighbours' bond matrices): one
+//    16-byte load per lane leaves a copy of the 54 coefficients in each
+//    16-lane row, and each multiply-add takes its coefficient by a DPP row
+//    broadcast.  The heat-bath half-sweeps read the 216-byte block of the
+//    per-site packed couplings [colour][H][54] with five scalar loads into
+//    SGPRs (one memory round trip per site, no vector registers);
 //  * every spin access is a 256-byte row: the layout of a group is
 //    [colour][H][component][64 lanes], each lane uses the same vector offset
 //    (4*lane), the site enters through the scalar offset and the component
@@ -19,12 +23,11 @@
 // the waves of the rows just before it.
 // The host runs all sweeps of one chain group back to back so that the
 // group stays in the 256 MB Infinity Cache between half-sweeps.  At L = 64
-// a group is 201 MB of spins; a half-sweep also reads its colour's packed
-// couplings (28.3 MB, 216 bytes a site), so one half-sweep touches 229 MB
-// and a whole sweep, both colours' couplings, 258 MB: slightly more than
-// the cache.  (Reading each bond once from the 108-byte canonical blocks
-// would make a sweep fit, but the four scattered scalar loads per site
-// measured slower than the one contiguous 216-byte block.)
+// a group is 201 MB of spins and its sample's canonical couplings 28 MB, so
+// a whole sweep touches 229 MB, which fits (with the packed blocks, 216
+// bytes a site, it would be 258 MB: slightly more than the cache).  Each
+// XCD walks its tiles backwards in the colour-1 half-sweeps, so that a
+// half-sweep starts where the previous one ended.
 #include <hip/hip_cooperative_groups.h>
 
 #include "kernels.hpp"
